@@ -1,0 +1,229 @@
+"""Throughput of the local-potential application V_loc|psi> on one MI355X.
+
+One step = one vloc_apply over the whole batch: 256 bands on a 96^3 grid with
+the |G| <= 24 sphere (57,777 plane waves, 1,793 z-sticks), K1 -> K2 -> K3 per
+band chunk.  Inputs are synthetic (seeded), resident in HBM before timing.
+Prints one JSON line on stdout; details go to stderr.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision f64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP64_PEAK = 78.6e12        # FLOP/s vector FP64
+FP32_PEAK_NONPACKED = 78.6e12  # FLOP/s FP32 without packed instructions
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "dft_codelets.h", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1601_07378_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(precision: str, nbands: int):
+    """HBM bytes per plane-kernel launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k2_plane_c2_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_band"]) * nbands
+    except (KeyError, ValueError):
+        return None
+
+
+def workload_sizes(plan, grid, nbands, precision):
+    st = plan.sticks()
+    nst = st.shape[0]
+    npw = plan.npw
+    nxo = plan.layout()["nxo"]
+    N1, N2, N3 = grid
+    N = N1 * N2 * N3
+    s = 16 if precision == "f64" else 8
+    sv = s // 2
+    # algorithmic bytes per band (c in, out out, one stick-buffer exchange per
+    # direction, V once per apply)
+    b_alg = 2 * npw * s + 4 * nst * N3 * s + N * sv / nbands
+    lg = np.log2
+    f_alg = 2 * (nst * 5 * N3 * lg(N3) + nxo * N3 * 5 * N2 * lg(N2) + N2 * N3 * 5 * N1 * lg(N1)) + 2 * N
+    return dict(nst=nst, npw=npw, nxo=nxo, N=N, s=s, sv=sv, b_alg=b_alg, f_alg=f_alg)
+
+
+def measure(precision, steps, warmup, chunk=0, timing=True):
+    import torch
+
+    import synth
+    from paper_1601_07378_amd import vloc
+
+    w = synth.WORKLOADS["c2_96"]
+    grid, cell, ecut, nb = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"]), w["nbands"]
+    plan = vloc.Plan(grid, cell, ecut, precision=precision, band_chunk=chunk)
+    hkl = plan.gvectors()
+    ct, rt = (torch.complex128, torch.float64) if precision == "f64" else (torch.complex64, torch.float32)
+    c = torch.from_numpy(synth.coefficients(hkl, nb)).to("cuda", ct)
+    V = torch.from_numpy(synth.potential(grid, w["ngauss"])).to("cuda", rt)
+    out = torch.empty_like(c)
+    stream = torch.cuda.current_stream()
+    plan.set_stream(stream)
+    for _ in range(warmup):
+        plan.apply(c, V, out=out, stream=stream)
+    torch.cuda.synchronize()
+    if timing:
+        plan.enable_timing(True)
+        plan.read_timing()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.apply(c, V, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    kms, kn = plan.read_timing() if timing else ([0, 0, 0], [0, 0, 0])
+    sizes = workload_sizes(plan, grid, nb, precision)
+    lay = plan.layout()
+    bal = plan.balance()
+    return dict(plan=plan, grid=grid, nb=nb, ms_total=ms_total, wall=wall, kms=kms, kn=kn,
+                sizes=sizes, layout=lay, balance=bal, out=out, c=c, V=V)
+
+
+def cpu_baseline(nbands_sample: int):
+    import oracle
+    import synth
+
+    w = synth.WORKLOADS["c2_96"]
+    grid, cell, ecut = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"])
+    hkl = oracle.sphere_py(cell, ecut)
+    c = synth.coefficients(hkl, w["nbands"])[:nbands_sample]
+    V = synth.potential(grid, w["ngauss"])
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.apply(grid, cell, ecut, (0, 0, 0), c, V, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=nbands_sample / dt, unit="bands/s", cores=threads, kind="oracle",
+                sample=f"first {nbands_sample} of the 256 bands of the 96^3/R=24 workload, "
+                       f"FP64, full-cube unpruned FFTs, OpenMP over bands; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the path shards over bands with no exchange, "
+              f"so --gpus {args.gpus} is not run (see the sharding notes in the design "
+              f"document).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"# device: {torch.cuda.get_device_name(0)}")
+    r = measure(args.precision, args.steps, args.warmup, args.chunk)
+    sz = r["sizes"]
+    nb = r["nb"]
+    ms_step = r["ms_total"] / args.steps
+    bands_per_s = nb * args.steps / (r["ms_total"] / 1e3)
+    kms, kn = r["kms"], r["kn"]
+    chunk = r["layout"]["band_chunk"]
+    # plane kernel (dominant): bytes per launch = S read + S written for its
+    # bands + V once
+    N3 = r["grid"][2]
+    b_k2_band = 2 * sz["nst"] * N3 * sz["s"]
+    k2_bytes = b_k2_band * nb * args.steps + sz["N"] * sz["sv"] * kn[1]
+    k2_time = kms[1] / 1e3
+    achieved = k2_bytes / k2_time if k2_time > 0 else None
+    log(f"# {args.precision}: {ms_step:.3f} ms/step, {bands_per_s:,.0f} bands/s; kernels ms/step "
+        f"K1 {kms[0] / args.steps:.3f} K2 {kms[1] / args.steps:.3f} K3 {kms[2] / args.steps:.3f}; "
+        f"launches {kn}; layout {r['layout']}")
+    path_frac = sz["b_alg"] * bands_per_s / HBM_PEAK
+    flop_rate = sz["f_alg"] * bands_per_s
+    bal = r["balance"]
+    log(f"# path: B_alg/band {sz['b_alg']:.0f} B -> {path_frac * 100:.1f}% of HBM peak; "
+        f"F_alg/band {sz['f_alg']:.3e} -> {flop_rate / 1e12:.1f} TFLOP/s; group PW max/min/mean "
+        f"{bal.max()}/{bal.min()}/{bal.mean():.1f}")
+    k2_launch_bytes = k2_bytes / kn[1] if kn[1] else None
+    traffic = read_traffic(args.precision, chunk)
+    result = {
+        "metric": "band V_loc|psi> applications/sec at 96^3 (FP64 vs FP32) + % HBM peak",
+        "value": round(bands_per_s, 1),
+        "unit": "bands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (seeded Gaussian coefficients scaled by 1/(1+|G|^2); V = 0.5 + 32 Gaussians)",
+        "config": {"workload": "96^3 grid, |G|<=24 sphere (57777 PW, 1793 sticks), 256 bands, Gamma, "
+                               "cubic cell", "grid": list(r["grid"]), "nbands": nb,
+                   "npw": sz["npw"], "band_chunk": chunk, "precision": args.precision},
+        "hbm_frac_path": round(path_frac, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_plane (K2)",
+                     "achieved": round(achieved / 1e9, 1) if achieved else None,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(k2_launch_bytes) if k2_launch_bytes else None,
+                     "avg_launch_ms": round(kms[1] / kn[1], 4) if kn[1] else None},
+        "kernel_ms_per_step": {"k1_stick_fwd": round(kms[0] / args.steps, 4),
+                               "k2_plane": round(kms[1] / args.steps, 4),
+                               "k3_stick_bwd": round(kms[2] / args.steps, 4)},
+    }
+    del r
+    torch.cuda.empty_cache()
+    if not args.no_f32 and args.precision == "f64":
+        r32 = measure("f32", args.steps, args.warmup, args.chunk, timing=False)
+        v32 = r32["nb"] * args.steps / (r32["ms_total"] / 1e3)
+        result["f32"] = {"value": round(v32, 1), "ms_per_step": round(r32["ms_total"] / args.steps, 4),
+                         "speedup_vs_f64": round(v32 / bands_per_s, 3),
+                         "hbm_frac_path": round(r32["sizes"]["b_alg"] * v32 / HBM_PEAK, 4)}
+        log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64)")
+        del r32
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(args.cpu_sample)
+        result["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()}
+        log(f"# cpu oracle: {cb['value']:.2f} bands/s on {cb['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

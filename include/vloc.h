@@ -1,0 +1,155 @@
+/*
+ * vloc.h -- C ABI of libvloc: the local-potential action V_loc|psi> on a batch
+ * of plane-wave wave functions, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gao, Mo, Fang, Wang, "Parallel 3-dim fast Fourier transforms with
+ * load balancing of the plane waves" (arXiv:1601.07378).
+ *   - Plane-wave expansion and its sign: Sec. 2, eq. 2.
+ *   - Cutoff sphere: Sec. 2, eq. 3.
+ *   - The operator (to real space, multiply by the diagonal V, back): Sec. 2,
+ *     the paragraph after eq. 3.
+ *   - Compact 3-D FFT (first pass only on columns meeting the sphere, second
+ *     only on columns meeting that cylinder, third on the whole cube): Sec. 4.3.
+ *   - Greedy distribution of columns by plane-wave count: Sec. 3.2.
+ *
+ * For each band n and each g = (h, k, l) of the sphere S:
+ *   psi_n(j)  = sum_{g in S} c_n(g) exp(-2 pi i (h j1/N1 + k j2/N2 + l j3/N3))
+ *   out_n(g)  = (1/N) sum_j exp(+2 pi i (h j1/N1 + k j2/N2 + l j3/N3)) V(j) psi_n(j)
+ * with N = N1 N2 N3 and j over the whole grid.
+ *   S = { g in Z^3 : |k+G|^2 <= 2 Ecut (1 + 1e-12) },  G = h b1 + k b2 + l b3,
+ *   b = 2 pi A^{-T} where the rows of A are the cell vectors a1, a2, a3.
+ * The cutoff is read as non-strict with a relative slack of 1e-12 (eq. 3 prints
+ * a strict inequality; on integer-radius spheres the shell is then kept).
+ * k enters only through S: V is lattice periodic, so exp(-i k.r) cancels
+ * between the two transforms and the grids hold the periodic part.
+ *
+ * Layouts (all contiguous, interleaved complex = {re, im}):
+ *   c, out : [nbands][npw] complex, in the plan's canonical G order
+ *            (lexicographic on signed (h, k, l); see vloc_plan_gvectors).
+ *   V      : [N3][N2][N1] real, x (j1) fastest.
+ *   psi_r  : [nbands][N3][N2][N1] complex (diagnostic transforms only).
+ * Element type follows the plan's precision: double / double-complex for
+ * VLOC_F64, float / float-complex for VLOC_F32.  All data pointers passed to
+ * vloc_apply, vloc_g2r and vloc_r2g are DEVICE pointers, at least 16-byte
+ * (F64) or 8-byte (F32) aligned; the caller owns them.
+ *
+ * Every call returns a vloc_status; nothing throws or aborts.  Detail of the
+ * last failure on the calling thread: vloc_last_error().
+ */
+#ifndef VLOC_H
+#define VLOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vloc_plan_s *vloc_plan; /* opaque; owned by the library */
+
+typedef enum {
+    VLOC_OK = 0,
+    VLOC_E_INVALID = -1, /* NULL pointer, negative count, bad option            */
+    VLOC_E_GRID = -2,    /* N_i < 1, N_i > 256, or a length the FFT cannot split */
+    VLOC_E_CELL = -3,    /* det(cell) <= 0 or non-finite cell                    */
+    VLOC_E_SPHERE = -4,  /* empty sphere, bad Ecut/k, or the sphere's extent on  */
+                         /* some axis is >= N_i (two points alias on the grid)  */
+    VLOC_E_ALIAS = -5,   /* out overlaps c or V                                 */
+    VLOC_E_NOMEM = -6,   /* host or device allocation failed                    */
+    VLOC_E_DEVICE = -7   /* HIP runtime error (no device, launch failure, ...)  */
+} vloc_status;
+
+typedef enum { VLOC_F64 = 0, VLOC_F32 = 1 } vloc_precision;
+
+/* Deal of z-sticks (columns meeting the sphere) to stick groups; each group is
+ * one workgroup of the two stick-transform kernels.  GREEDY is the paper's
+ * rule (sort by descending plane-wave count, ties in canonical order, deal in
+ * turn; Sec. 3.2); SNAKE reverses every other pass; CONTIGUOUS keeps canonical
+ * order (no balancing). */
+typedef enum { VLOC_DEAL_GREEDY = 0, VLOC_DEAL_SNAKE = 1, VLOC_DEAL_CONTIGUOUS = 2 } vloc_deal;
+
+/* Zero-initialised options mean: F64, greedy deal, automatic sizes. */
+typedef struct {
+    int32_t precision;        /* vloc_precision                                    */
+    int32_t deal;             /* vloc_deal                                         */
+    int32_t sticks_per_group; /* 0 = automatic; else 1..64                         */
+    int32_t band_chunk;       /* bands per internal chunk; 0 = automatic           */
+    int32_t plane_rows;       /* rows per x-pass batch in the plane kernel; 0=auto  */
+    int32_t plane_threads;    /* threads per plane workgroup (64..1024, mult. of 64);
+                                 0 = automatic                                     */
+} vloc_options;
+
+/* Build a plan (host work only; device tables are uploaded on first use).
+ *   grid : {N1, N2, N3}, each in [1, 256] and a product L1*L2 of factors
+ *          in {1,2,3,4,5,6,8,9,10,12,15,16} (every 2,3,5-smooth length up to
+ *          256 except 125, 243 and 250).
+ *   cell : rows a1, a2, a3 (bohr), det > 0.
+ *   ecut : Hartree; the sphere keeps |k+G|^2 <= 2 ecut (1 + 1e-12).
+ *   k    : reduced coordinates in the reciprocal basis b1, b2, b3.
+ * Errors: VLOC_E_INVALID (NULL), VLOC_E_GRID, VLOC_E_CELL, VLOC_E_SPHERE,
+ * VLOC_E_NOMEM.  On error *plan is set to NULL. */
+vloc_status vloc_plan_create(vloc_plan *plan, const int32_t grid[3], const double cell[9],
+                             double ecut, const double k[3]);
+/* As vloc_plan_create, with options (NULL = defaults). */
+vloc_status vloc_plan_create_ex(vloc_plan *plan, const int32_t grid[3], const double cell[9],
+                                double ecut, const double k[3], const vloc_options *opt);
+/* Frees host and device resources; NULL is a no-op.  Waits for the plan's
+ * stream before freeing device memory. */
+vloc_status vloc_plan_destroy(vloc_plan plan);
+
+/* Stream on which the plan enqueues work (a hipStream_t; NULL = the null
+ * stream).  The plan does not own the stream. */
+vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream);
+
+/* out[n] = V_loc c[n] for n < nbands (definition above).  Stream-ordered and
+ * asynchronous: returns after enqueueing.  nbands == 0 is a no-op that returns
+ * VLOC_OK.  out must not overlap c or V (VLOC_E_ALIAS); c and V are not
+ * modified.  The plan owns an internal stick buffer sized for one band chunk,
+ * allocated on first use; calls on one plan must not run concurrently. */
+vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void *V, void *out);
+
+/* ---------------------------------------------------------------- queries */
+/* Host outputs, caller-allocated. */
+vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw);
+/* hkl: npw*3 int32 (h, k, l) in canonical order. */
+vloc_status vloc_plan_gvectors(vloc_plan plan, int32_t *hkl);
+/* Stick table in canonical order: nsticks rows of (h, k, offset, count, lmin),
+ * where the run c[offset .. offset+count) holds l = lmin .. lmin+count-1.
+ * table may be NULL to query the count only. */
+vloc_status vloc_plan_sticks(vloc_plan plan, int64_t *nsticks, int32_t *table);
+/* Plane waves per stick group after the deal (the load-balance statistic of
+ * the paper's Tab. 2, per workgroup instead of per process).  pw_per_group may
+ * be NULL to query the count only. */
+vloc_status vloc_plan_balance(vloc_plan plan, int64_t *ngroups, int64_t *pw_per_group);
+/* Group of each stick (canonical stick order), nsticks int32. */
+vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
+/* Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
+ * sticks_per_group, band_chunk}; out[8..11] = {plane_rows, plane_threads,
+ * plane_lds_bytes, nxo} where nxo is the number of occupied x-planes. */
+vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[12]);
+
+/* ------------------------------------------------------- kernel timing */
+/* When enabled, the plan records HIP events on its stream around each of its
+ * kernel launches (stick forward K1, plane K2, stick backward K3).  Adds a few
+ * microseconds per launch; meant for profiling runs. */
+vloc_status vloc_plan_enable_timing(vloc_plan plan, int32_t enable);
+/* Waits for the recorded events, writes the summed milliseconds of K1, K2, K3
+ * into ms[3] and their launch counts into launches[3] (either may be NULL),
+ * and resets the record. */
+vloc_status vloc_plan_read_timing(vloc_plan plan, double ms[3], int64_t launches[3]);
+
+/* ------------------------------------------- diagnostic full-grid transforms */
+/* Same conventions as vloc_apply: psi_r[n] = psi_n on the whole grid. */
+vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r);
+/* c_out[n](g) = (1/N) sum_j exp(+2 pi i g.j/N) psi_r[n](j) for g in S. */
+vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_out);
+
+/* Static description of a status code. */
+const char *vloc_status_string(vloc_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *vloc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLOC_H */

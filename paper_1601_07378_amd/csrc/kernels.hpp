@@ -1,0 +1,44 @@
+// kernels.hpp -- launch interface of the three transform kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace vloc {
+
+enum PlaneMode { MODE_APPLY = 0, MODE_G2R = 1, MODE_R2G = 2 };
+
+// Tables and sizes shared by the kernels of one plan (device pointers).
+struct DevTables {
+    const int4 *slot_info;  // per slot: {offset, count, lmin mod N3, plane position}
+    const int2 *groups;     // per group: {first slot, number of sticks}
+    const void *twx, *twy, *twz; // exp(-2 pi i j / L), complex of the plan precision
+};
+
+struct Geometry {
+    int N1, N2, N3;
+    int L1x, L2x, L1y, L2y, L1z, L2z;
+    int nxo;        // occupied x-planes
+    int hmin_mod;   // hmin mod N1
+    int ldy, ldx, ldz;
+    int rows;       // x rows per batch in the plane kernel
+    int nst, npw, ngroups;
+    int group_cap;  // most sticks in one group
+    double inv_n;   // 1 / (N1 N2 N3)
+};
+
+// K1: stick z-transforms (G -> r direction) from c into the stick buffer S.
+// S layout: [band][z][slot].
+template <typename T>
+hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const void *c, int64_t band0,
+                            int nb, void *S, int threads, hipStream_t st);
+// K2: plane kernel.  APPLY: S -> S in place.  G2R: S -> psi rows.  R2G: psi -> S.
+template <typename T>
+hipError_t launch_plane(const Geometry &g, const DevTables &t, int mode, void *S, const void *V,
+                        void *psi, int64_t band0, int nb, int threads, int lds_bytes,
+                        hipStream_t st);
+// K3: stick z-transforms (r -> G direction) with 1/N, gathering into out.
+template <typename T>
+hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S, void *out,
+                            int64_t band0, int nb, int threads, hipStream_t st);
+
+} // namespace vloc

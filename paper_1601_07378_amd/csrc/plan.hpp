@@ -1,0 +1,61 @@
+// plan.hpp -- host-side plan of the compact local-potential application.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vloc.h"
+
+namespace vloc {
+
+// One z-stick: the sphere points sharing (h, k); a contiguous run of c.
+struct Stick {
+    int32_t h, k, offset, count, lmin;
+};
+
+// How a line of length L is split into two register codelets, L = L1 * L2.
+struct Split {
+    int L = 0, L1 = 0, L2 = 0;
+};
+
+struct HostPlan {
+    int32_t grid[3] = {0, 0, 0};
+    double cell[9] = {};
+    double ecut = 0.0;
+    double kpt[3] = {};
+    vloc_options opt{};
+
+    std::vector<int32_t> hkl;      // npw * 3, canonical order
+    std::vector<Stick> sticks;     // canonical (h, k) order
+    int32_t hmin = 0, hmax = 0, kmin = 0, kmax = 0, nxo = 0;
+
+    // deal of sticks to groups; slots are numbered so that each group's
+    // sticks are contiguous
+    int32_t ngroups = 0, group_cap = 0;
+    std::vector<int32_t> group_of_stick;   // canonical stick -> group
+    std::vector<int32_t> stick_of_slot;    // slot -> canonical stick
+    std::vector<int32_t> group_start, group_size;
+
+    Split sx, sy, sz;
+    int32_t band_chunk = 0;   // bands per internal chunk
+    int32_t plane_rows = 0;   // x-pass rows per batch in the plane kernel
+    int32_t plane_threads = 0;
+    int32_t plane_lds = 0;    // bytes of LDS per plane workgroup
+    int32_t stick_threads = 0;
+    int32_t ldy = 0, ldx = 0, ldz = 0; // LDS line strides (complex elements)
+
+    int64_t npw() const { return (int64_t)hkl.size() / 3; }
+    int64_t nst() const { return (int64_t)sticks.size(); }
+    int elem_bytes() const { return opt.precision == VLOC_F32 ? 8 : 16; }
+};
+
+// Builds everything host-side; returns VLOC_OK or an error with a message.
+vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cell[9], double ecut,
+                            const double k[3], const vloc_options *opt, std::string &err);
+
+bool split_length(int L, Split &s);
+
+// exp(-2 pi i j / L) for j < L, FP64, angle numerator reduced exactly.
+std::vector<double> twiddle_table(int L);
+
+} // namespace vloc

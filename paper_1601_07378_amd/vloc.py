@@ -1,0 +1,243 @@
+"""Python binding of libvloc (ctypes).  Argument marshalling only: every step of
+the transform runs in the HIP kernels of libvloc.so; torch is used for device
+memory and the current stream.
+
+Names follow the C ABI in include/vloc.h.  If the shared library is missing the
+import fails loudly: there is no CPU fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvloc.so")
+
+VLOC_OK = 0
+VLOC_E_INVALID = -1
+VLOC_E_GRID = -2
+VLOC_E_CELL = -3
+VLOC_E_SPHERE = -4
+VLOC_E_ALIAS = -5
+VLOC_E_NOMEM = -6
+VLOC_E_DEVICE = -7
+VLOC_F64 = 0
+VLOC_F32 = 1
+DEALS = {"greedy": 0, "snake": 1, "contiguous": 2}
+
+# Every function the header declares; tests check each is exported.
+EXPORTS = [
+    "vloc_plan_create", "vloc_plan_create_ex", "vloc_plan_destroy", "vloc_set_stream",
+    "vloc_apply", "vloc_plan_npw", "vloc_plan_gvectors", "vloc_plan_sticks",
+    "vloc_plan_balance", "vloc_plan_stick_groups", "vloc_plan_layout", "vloc_g2r", "vloc_r2g",
+    "vloc_status_string", "vloc_last_error", "vloc_plan_enable_timing", "vloc_plan_read_timing",
+]
+
+
+class VlocError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"vloc status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("deal", ctypes.c_int32),
+                ("sticks_per_group", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
+                ("plane_rows", ctypes.c_int32), ("plane_threads", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_1601_07378_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "vloc_plan_create": [ctypes.POINTER(vp), i32p, dp, ctypes.c_double, dp],
+        "vloc_plan_create_ex": [ctypes.POINTER(vp), i32p, dp, ctypes.c_double, dp,
+                                ctypes.POINTER(Options)],
+        "vloc_plan_destroy": [vp],
+        "vloc_set_stream": [vp, vp],
+        "vloc_apply": [vp, vp, i64, vp, vp],
+        "vloc_plan_npw": [vp, i64p],
+        "vloc_plan_gvectors": [vp, i32p],
+        "vloc_plan_sticks": [vp, i64p, i32p],
+        "vloc_plan_balance": [vp, i64p, i64p],
+        "vloc_plan_stick_groups": [vp, i32p],
+        "vloc_plan_layout": [vp, i32p],
+        "vloc_g2r": [vp, vp, i64, vp],
+        "vloc_r2g": [vp, vp, i64, vp],
+        "vloc_plan_enable_timing": [vp, ctypes.c_int32],
+        "vloc_plan_read_timing": [vp, ctypes.POINTER(ctypes.c_double), i64p],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.vloc_status_string.argtypes = [ctypes.c_int]
+    L.vloc_status_string.restype = ctypes.c_char_p
+    L.vloc_last_error.argtypes = []
+    L.vloc_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != VLOC_OK:
+        msg = lib().vloc_last_error().decode()
+        raise VlocError(status, msg or lib().vloc_status_string(status).decode())
+
+
+def _i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """A V_loc plan: grid (N1, N2, N3), cell rows a1..a3, E_cut (Hartree), k in
+    reduced coordinates; precision 'f64' or 'f32'."""
+
+    def __init__(self, grid, cell, ecut: float, k=(0.0, 0.0, 0.0), precision: str = "f64",
+                 deal: str = "greedy", sticks_per_group: int = 0, band_chunk: int = 0,
+                 plane_rows: int = 0, plane_threads: int = 0):
+        self._h = ctypes.c_void_p()
+        g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32).reshape(3))
+        c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+        kk = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(3))
+        if precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        opt = Options(VLOC_F64 if precision == "f64" else VLOC_F32, DEALS[deal],
+                      sticks_per_group, band_chunk, plane_rows, plane_threads)
+        check(lib().vloc_plan_create_ex(ctypes.byref(self._h), _i32(g), _f64(c), float(ecut),
+                                        _f64(kk), ctypes.byref(opt)))
+        self.grid = tuple(int(x) for x in g)
+        self.precision = precision
+        n = ctypes.c_int64()
+        check(lib().vloc_plan_npw(self._h, ctypes.byref(n)))
+        self.npw = int(n.value)
+
+    def close(self):
+        if self._h:
+            lib().vloc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- queries
+    def gvectors(self) -> np.ndarray:
+        out = np.empty((self.npw, 3), dtype=np.int32)
+        check(lib().vloc_plan_gvectors(self._h, _i32(out)))
+        return out
+
+    def sticks(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        check(lib().vloc_plan_sticks(self._h, ctypes.byref(n), None))
+        out = np.empty((n.value, 5), dtype=np.int32)
+        check(lib().vloc_plan_sticks(self._h, ctypes.byref(n), _i32(out)))
+        return out
+
+    def balance(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        check(lib().vloc_plan_balance(self._h, ctypes.byref(n), None))
+        out = np.empty(n.value, dtype=np.int64)
+        check(lib().vloc_plan_balance(self._h, ctypes.byref(n),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return out
+
+    def stick_groups(self) -> np.ndarray:
+        out = np.empty(self.sticks().shape[0], dtype=np.int32)
+        check(lib().vloc_plan_stick_groups(self._h, _i32(out)))
+        return out
+
+    def layout(self) -> dict:
+        v = np.empty(12, dtype=np.int32)
+        check(lib().vloc_plan_layout(self._h, _i32(v)))
+        keys = ["L1x", "L2x", "L1y", "L2y", "L1z", "L2z", "sticks_per_group", "band_chunk",
+                "plane_rows", "plane_threads", "plane_lds_bytes", "nxo"]
+        return dict(zip(keys, (int(x) for x in v)))
+
+    # ---- per-kernel timing (HIP events around each launch on the plan stream)
+    def enable_timing(self, on: bool = True):
+        check(lib().vloc_plan_enable_timing(self._h, 1 if on else 0))
+
+    def read_timing(self):
+        """Summed ms and launch counts of (stick forward, plane, stick backward)."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        check(lib().vloc_plan_read_timing(self._h, ms, n))
+        return list(ms), list(n)
+
+    # ---- device work (torch tensors on the GPU)
+    def _dtypes(self):
+        import torch
+        return (torch.complex128, torch.float64) if self.precision == "f64" else \
+            (torch.complex64, torch.float32)
+
+    def set_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib().vloc_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def apply(self, c, V, out=None, stream=None):
+        """out[n] = V_loc c[n]; c (nb, npw) complex, V (N3, N2, N1) real, on the GPU."""
+        import torch
+        ct, rt = self._dtypes()
+        if c.dtype != ct or V.dtype != rt:
+            raise TypeError(f"expected c {ct} and V {rt}")
+        if not (c.is_cuda and V.is_cuda):
+            raise ValueError("c and V must be device tensors")
+        if c.dim() != 2 or c.shape[1] != self.npw or not c.is_contiguous():
+            raise ValueError("c must be contiguous (nbands, npw)")
+        if V.numel() != self.grid[0] * self.grid[1] * self.grid[2] or not V.is_contiguous():
+            raise ValueError("V must be contiguous with N3*N2*N1 values")
+        if out is None:
+            out = torch.empty_like(c)
+        self.set_stream(stream)
+        check(lib().vloc_apply(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
+                               ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def g2r(self, c, out=None, stream=None):
+        import torch
+        ct, _ = self._dtypes()
+        if c.dtype != ct or not c.is_cuda or not c.is_contiguous() or c.shape[1] != self.npw:
+            raise ValueError("c must be a contiguous device tensor (nbands, npw)")
+        N1, N2, N3 = self.grid
+        if out is None:
+            out = torch.empty((c.shape[0], N3, N2, N1), dtype=ct, device=c.device)
+        self.set_stream(stream)
+        check(lib().vloc_g2r(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
+                             ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def r2g(self, psi, out=None, stream=None):
+        import torch
+        ct, _ = self._dtypes()
+        if psi.dtype != ct or not psi.is_cuda or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous device tensor (nbands, N3, N2, N1)")
+        if out is None:
+            out = torch.empty((psi.shape[0], self.npw), dtype=ct, device=psi.device)
+        self.set_stream(stream)
+        check(lib().vloc_r2g(self._h, ctypes.c_void_p(psi.data_ptr()), psi.shape[0],
+                             ctypes.c_void_p(out.data_ptr())))
+        return out

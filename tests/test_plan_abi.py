@@ -1,0 +1,168 @@
+"""Host-side checks of libvloc (CPU only, no kernel launches).
+
+* every function declared in include/vloc.h is exported;
+* the plan's sphere, canonical G order, stick table and greedy deal equal the
+  oracle's independent Python enumeration, bit for bit;
+* argument validation returns the documented status before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import ROOT, gpu_available
+
+vloc = pytest.importorskip("paper_1601_07378_amd.vloc")
+
+SKEW = np.array([[6.0, 0.3, -0.2], [0.5, 7.0, 0.4], [-0.3, 0.6, 6.5]])
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "vloc.h")).read()
+    names = set(re.findall(r"\b(vloc_[a-z0-9_]+)\s*\(", hdr))
+    assert names, "no declarations found"
+    assert names == set(vloc.EXPORTS)
+    L = vloc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+CASES = [
+    ((24, 24, 24), synth.cubic_cell(), 18.0, (0, 0, 0)),
+    ((96, 96, 96), synth.cubic_cell(), 288.0, (0, 0, 0)),
+    ((128, 128, 128), synth.cubic_cell(), 512.0, (0, 0, 0)),
+    ((80, 80, 80), synth.cubic_cell(), 206.5, (0, 0, 0)),
+    ((72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0, 0)),
+    ((72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0.25, 0)),
+    ((72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0.25, 0.25)),
+    ((16, 18, 20), SKEW, 12.0, (0.25, 1 / 3, 0.0)),
+    ((15, 9, 10), SKEW * np.array([[1.0], [0.6], [0.7]]), 5.0, (0.1, -0.2, 0.3)),
+]
+
+
+@pytest.mark.parametrize("grid,cell,ecut,k", CASES)
+def test_stick_map_matches_oracle(grid, cell, ecut, k):
+    """T9: G list, stick table, occupied range, deal and balance, bit-exact."""
+    p = vloc.Plan(grid, cell, ecut, k)
+    ref = oracle.sphere_py(cell, ecut, k)
+    assert np.array_equal(p.gvectors(), ref)
+    st_ref = oracle.sticks(ref)
+    assert np.array_equal(p.sticks().astype(np.int64), st_ref)
+    lay = p.layout()
+    assert lay["nxo"] == st_ref[:, 0].max() - st_ref[:, 0].min() + 1
+    ng = p.balance().size
+    g_ref, _ = oracle.greedy_deal(st_ref[:, 3], ng, "cyclic")
+    assert np.array_equal(p.stick_groups(), g_ref)
+    assert np.array_equal(p.balance(), oracle.group_loads(st_ref[:, 3], g_ref, ng))
+    ps = vloc.Plan(grid, cell, ecut, k, deal="snake")
+    gs_ref, _ = oracle.greedy_deal(st_ref[:, 3], ng, "snake")
+    assert np.array_equal(ps.stick_groups(), gs_ref)
+
+
+def test_known_counts():
+    p = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0)
+    assert (p.npw, p.sticks().shape[0]) == (925, 113)
+    p = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0)
+    assert (p.npw, p.sticks().shape[0], p.layout()["nxo"]) == (57777, 1793, 49)
+
+
+def test_greedy_balance_beats_unsorted():
+    """Tab. 2's statistic per workgroup: the sorted deal narrows max-min."""
+    p = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, sticks_per_group=28)
+    loads = p.balance()
+    st = p.sticks()
+    g_u, _ = oracle.greedy_deal(st[:, 3], loads.size, "unsorted")
+    lu = oracle.group_loads(st[:, 3], g_u, loads.size)
+    assert loads.max() - loads.min() < lu.max() - lu.min()
+    assert loads.max() - loads.min() <= st[:, 3].max()
+
+
+def _create(grid, cell=None, ecut=18.0, k=(0, 0, 0), opt=None):
+    L = vloc.lib()
+    h = ctypes.c_void_p()
+    g = np.asarray(grid, dtype=np.int32)
+    c = np.ascontiguousarray(np.asarray(synth.cubic_cell() if cell is None else cell,
+                                        dtype=np.float64).reshape(9))
+    kk = np.asarray(k, dtype=np.float64)
+    o = ctypes.byref(opt) if opt is not None else None
+    s = L.vloc_plan_create_ex(ctypes.byref(h), vloc._i32(g), vloc._f64(c), ecut, vloc._f64(kk), o)
+    return s, h
+
+
+@pytest.mark.parametrize("grid,status", [((7, 24, 24), vloc.VLOC_E_GRID),
+                                         ((14, 24, 24), vloc.VLOC_E_GRID),
+                                         ((250, 24, 24), vloc.VLOC_E_GRID),
+                                         ((257, 24, 24), vloc.VLOC_E_GRID),
+                                         ((0, 24, 24), vloc.VLOC_E_GRID),
+                                         ((24, 24, 24), vloc.VLOC_OK)])
+def test_grid_validation(grid, status):
+    s, h = _create(grid)
+    assert s == status
+    assert (h.value is None) == (status != vloc.VLOC_OK)
+    vloc.lib().vloc_plan_destroy(h)
+
+
+def test_sphere_and_cell_validation():
+    assert _create((24, 24, 24), ecut=0.5 * 12 ** 2)[0] == vloc.VLOC_E_SPHERE  # extent 25 > 24
+    assert _create((24, 24, 24), ecut=0.0)[0] == vloc.VLOC_E_SPHERE
+    assert _create((24, 24, 24), ecut=float("nan"))[0] == vloc.VLOC_E_SPHERE
+    assert _create((24, 24, 24), cell=-np.eye(3))[0] == vloc.VLOC_E_CELL
+    assert _create((24, 24, 24), cell=np.zeros((3, 3)))[0] == vloc.VLOC_E_CELL
+    bad = np.eye(3)
+    bad[0, 0] = float("inf")
+    assert _create((24, 24, 24), cell=bad)[0] == vloc.VLOC_E_CELL
+    assert _create((24, 24, 24), k=(float("nan"), 0, 0))[0] == vloc.VLOC_E_SPHERE
+    o = vloc.Options(7, 0, 0, 0, 0, 0)
+    assert _create((24, 24, 24), opt=o)[0] == vloc.VLOC_E_INVALID
+    o = vloc.Options(0, 0, 0, 0, 0, 100)
+    assert _create((24, 24, 24), opt=o)[0] == vloc.VLOC_E_INVALID
+    L = vloc.lib()
+    assert L.vloc_plan_create(None, None, None, 1.0, None) == vloc.VLOC_E_INVALID
+    assert L.vloc_plan_destroy(None) == vloc.VLOC_OK
+    assert b"NULL" in L.vloc_last_error() or L.vloc_last_error()
+
+
+def test_apply_argument_validation_before_device():
+    """Checks that return before any HIP call; the pointers are never dereferenced."""
+    L = vloc.lib()
+    p = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0)
+    h = p._h
+    fake_c, fake_v = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x40000000)
+    assert L.vloc_apply(h, fake_c, 0, fake_v, fake_c) == vloc.VLOC_OK  # no-op
+    assert L.vloc_apply(h, fake_c, -1, fake_v, ctypes.c_void_p(0x20000000)) == vloc.VLOC_E_INVALID
+    assert L.vloc_apply(h, None, 3, fake_v, ctypes.c_void_p(0x20000000)) == vloc.VLOC_E_INVALID
+    assert L.vloc_apply(h, fake_c, 3, fake_v, fake_c) == vloc.VLOC_E_ALIAS
+    # out starts inside c's 3 bands
+    assert L.vloc_apply(h, fake_c, 3, fake_v, ctypes.c_void_p(0x10000000 + 16 * 925)) == \
+        vloc.VLOC_E_ALIAS
+    assert L.vloc_apply(h, fake_c, 3, fake_v, ctypes.c_void_p(0x40000000 - 16)) == \
+        vloc.VLOC_E_ALIAS
+    assert L.vloc_apply(h, ctypes.c_void_p(0x10000008), 3, fake_v,
+                        ctypes.c_void_p(0x20000000)) == vloc.VLOC_E_INVALID  # misaligned
+    assert L.vloc_apply(None, fake_c, 1, fake_v, fake_c) == vloc.VLOC_E_INVALID
+    assert L.vloc_g2r(h, fake_c, 2, fake_c) == vloc.VLOC_E_ALIAS
+    assert L.vloc_r2g(h, fake_c, 0, fake_c) == vloc.VLOC_OK
+    assert L.vloc_status_string(vloc.VLOC_E_ALIAS) == b"output overlaps an input"
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the no-device path")
+def test_apply_without_device_reports_device_error():
+    L = vloc.lib()
+    p = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0)
+    s = L.vloc_apply(p._h, ctypes.c_void_p(0x10000000), 1, ctypes.c_void_p(0x40000000),
+                     ctypes.c_void_p(0x20000000))
+    assert s == vloc.VLOC_E_DEVICE
+    assert L.vloc_last_error()
+
+
+def test_layout_defaults():
+    p = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0)
+    lay = p.layout()
+    assert (lay["L1x"], lay["L2x"]) == (8, 12)
+    assert lay["plane_lds_bytes"] <= 160 * 1024
+    assert lay["sticks_per_group"] * max(lay["L1z"], lay["L2z"]) <= 256
+    pf = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, precision="f32")
+    assert pf.layout()["plane_lds_bytes"] < lay["plane_lds_bytes"]

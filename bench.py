@@ -143,6 +143,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain device copy of 256 MiB so that "
+                         "profiler byte counters can be scaled by a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the path shards over bands with no exchange, "
@@ -210,6 +213,14 @@ def main():
     }
     del r
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("# copy calibration: 268435456 B read + 268435456 B written")
+        del src, dst
     if not args.no_f32 and args.precision == "f64":
         r32 = measure("f32", args.steps, args.warmup, args.chunk, timing=False)
         v32 = r32["nb"] * args.steps / (r32["ms_total"] / 1e3)

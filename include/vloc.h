@@ -74,9 +74,16 @@ typedef struct {
     int32_t deal;             /* vloc_deal                                         */
     int32_t sticks_per_group; /* 0 = automatic; else 1..64                         */
     int32_t band_chunk;       /* bands per internal chunk; 0 = automatic           */
-    int32_t plane_rows;       /* rows per x-pass batch in the plane kernel; 0=auto  */
-    int32_t plane_threads;    /* threads per plane workgroup (64..1024, mult. of 64);
-                                 0 = automatic                                     */
+    int32_t plane_rows;       /* rows per x-pass batch of one wavefront in the plane
+                                 kernel; 0 = automatic                             */
+    int32_t plane_threads;    /* threads per plane workgroup (64..512, multiple of
+                                 64); 0 = automatic                                */
+    int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
+                                 pass (each with its own row buffer); 0 = auto     */
+    int32_t plane_xmode;      /* x pass of the plane kernel: 0 = automatic, 1 = row
+                                 buffers in LDS, 2 = one lane quad per row (needs
+                                 N1 in {24, 72, 80, 96} with the matching y split
+                                 and N2 <= 128)                                    */
 } vloc_options;
 
 /* Build a plan (host work only; device tables are uploaded on first use).
@@ -124,9 +131,10 @@ vloc_status vloc_plan_balance(vloc_plan plan, int64_t *ngroups, int64_t *pw_per_
 /* Group of each stick (canonical stick order), nsticks int32. */
 vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
 /* Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
- * sticks_per_group, band_chunk}; out[8..11] = {plane_rows, plane_threads,
- * plane_lds_bytes, nxo} where nxo is the number of occupied x-planes. */
-vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[12]);
+ * sticks_per_group, band_chunk}; out[8..13] = {plane_rows, plane_threads,
+ * plane_lds_bytes, nxo, plane_xwaves, plane_xmode} where nxo is the number of
+ * occupied x-planes and plane_xmode is 1 (row buffers) or 2 (lane quads). */
+vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14]);
 
 /* ------------------------------------------------------- kernel timing */
 /* When enabled, the plan records HIP events on its stream around each of its

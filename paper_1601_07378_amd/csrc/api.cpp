@@ -26,7 +26,9 @@ struct vloc_plan_s {
     int device = -1;
     int4 *d_slot = nullptr;
     int2 *d_groups = nullptr;
+    int2 *d_cols = nullptr;
     void *d_tw[3] = {nullptr, nullptr, nullptr};
+    double2 *d_twx64 = nullptr;
     void *d_S = nullptr;
     size_t S_bytes = 0;
     Geometry geo{};
@@ -57,6 +59,10 @@ void free_device(vloc_plan p)
 {
     if (p->d_slot) (void)hipFree(p->d_slot);
     if (p->d_groups) (void)hipFree(p->d_groups);
+    if (p->d_cols) (void)hipFree(p->d_cols);
+    if (p->d_twx64) (void)hipFree(p->d_twx64);
+    p->d_twx64 = nullptr;
+    p->d_cols = nullptr;
     for (void *&t : p->d_tw)
         if (t) (void)hipFree(t), t = nullptr;
     if (p->d_S) (void)hipFree(p->d_S);
@@ -89,7 +95,13 @@ vloc_status upload(vloc_plan p)
     std::vector<int2> groups(h.ngroups);
     for (int g = 0; g < h.ngroups; ++g) groups[g] = make_int2(h.group_start[g], h.group_size[g]);
 
+    std::vector<int2> cols(h.nxo);
+    for (int c = 0; c < h.nxo; ++c) cols[c] = make_int2(h.col_kmin[c], h.col_kcnt[c]);
     if ((e = hipMalloc(&p->d_slot, sizeof(int4) * nst)) != hipSuccess) goto nomem;
+    if ((e = hipMalloc(&p->d_cols, sizeof(int2) * h.nxo)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(p->d_cols, cols.data(), sizeof(int2) * h.nxo, hipMemcpyHostToDevice)) !=
+        hipSuccess)
+        goto devfail;
     if ((e = hipMalloc(&p->d_groups, sizeof(int2) * h.ngroups)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(p->d_slot, slot.data(), sizeof(int4) * nst, hipMemcpyHostToDevice)) !=
         hipSuccess)
@@ -118,6 +130,13 @@ vloc_status upload(vloc_plan p)
         }
     }
     {
+        std::vector<double> t64 = twiddle_table(h.sx.L);
+        if ((e = hipMalloc(&p->d_twx64, t64.size() * sizeof(double))) != hipSuccess) goto nomem;
+        if ((e = hipMemcpy(p->d_twx64, t64.data(), t64.size() * sizeof(double),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            goto devfail;
+    }
+    {
         Geometry &g = p->geo;
         g.N1 = h.grid[0];
         g.N2 = h.grid[1];
@@ -134,6 +153,10 @@ vloc_status upload(vloc_plan p)
         g.ldx = h.ldx;
         g.ldz = h.ldz;
         g.rows = h.plane_rows;
+        g.rb = h.plane_rb;
+        g.rl = h.plane_rl;
+        g.xw = h.plane_xw;
+        g.xq = h.plane_xq;
         g.nst = (int)nst;
         g.npw = (int)h.npw();
         g.ngroups = h.ngroups;
@@ -188,9 +211,11 @@ DevTables tables(vloc_plan p)
     DevTables t;
     t.slot_info = p->d_slot;
     t.groups = p->d_groups;
+    t.cols = p->d_cols;
     t.twx = p->d_tw[0];
     t.twy = p->d_tw[1];
     t.twz = p->d_tw[2];
+    t.twx64 = p->d_twx64;
     return t;
 }
 
@@ -438,13 +463,14 @@ vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick)
     return VLOC_OK;
 }
 
-vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[12])
+vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14])
 {
     if (!plan || !out) return fail(VLOC_E_INVALID, "NULL argument");
     const HostPlan &h = plan->hp;
-    int32_t v[12] = {h.sx.L1,      h.sx.L2,        h.sy.L1,         h.sy.L2,
-                     h.sz.L1,      h.sz.L2,        h.group_cap,     h.band_chunk,
-                     h.plane_rows, h.plane_threads, h.plane_lds,    h.nxo};
+    int32_t v[14] = {h.sx.L1,      h.sx.L2,         h.sy.L1,      h.sy.L2, h.sz.L1,
+                     h.sz.L2,      h.group_cap,     h.band_chunk, h.plane_rows,
+                     h.plane_threads, h.plane_lds, h.nxo,        h.plane_xw,
+                     h.plane_xq ? 2 : 1};
     std::memcpy(out, v, sizeof v);
     return VLOC_OK;
 }

@@ -212,24 +212,203 @@ __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
 
 // ------------------------------------------------------------------ K2
 // One workgroup per (band, z-plane).  LDS holds the occupied part of the plane,
-// P[h - hmin][y] (nxo columns of N2), plus a batch of full x rows.
-//   1. S[band][z][*] -> P (zero elsewhere);
-//   2. y transforms (-i) on the nxo columns: the cylinder -> cuboid step;
-//   3. per batch of rows: full x transform (-i), times V[z][y][x], x transform
-//      (+i), keeping only the nxo occupied outputs;
-//   4. y transforms (+i) on the nxo columns;
-//   5. P -> S[band][z][*] at the sticks' positions.
-// Real-space psi for the plane never leaves registers/LDS.  After step 2 the
+// P[h - hmin][y] (nxo columns of N2, column stride ldy), plus one private batch
+// of full x rows for each wavefront that takes part in the x pass.
+//   1. S[band][z][*] -> P at the sticks' positions;
+//   2. y transforms (-i) on the nxo columns (the cylinder -> cuboid step); a
+//      column's input is non-zero only on its own k range, so P needs no
+//      zero fill;
+//   3. x pass, wavefront-local: each wave takes a contiguous block of rows and
+//      runs, per batch of rows, the full x transform (-i), the multiply by
+//      V[z][y][x] and the x transform (+i), keeping only the nxo occupied
+//      outputs; only wave-level ordering is needed inside the pass;
+//   4. y transforms (+i) on the nxo columns, storing only the stick positions;
+//   5. P -> S[band][z][*].
+// Real-space psi of the plane never leaves registers/LDS.  After step 2 the
 // columns are in transposed order: row y sits at L2y (y mod L1y) + y / L1y.
-template <typename T, int MODE>
-__global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *__restrict__ S,
-                                               const T *__restrict__ V,
-                                               cx<T> *__restrict__ psi, long long band0, int nb)
+// Row buffers keep position p at p + p / L2x so that the strided stage-B
+// accesses hit distinct LDS banks; y stages map consecutive lanes to
+// consecutive columns (stride ldy, odd) for the same reason.
+
+// Compile-time size CT if non-zero, else the runtime r through the switch.
+template <int CT, typename F>
+__device__ __forceinline__ void with_size(int r, F &&f)
+{
+    if constexpr (CT > 0)
+        f(std::integral_constant<int, CT>{});
+    else
+        with_codelet(r, f);
+}
+
+// Orders LDS accesses of one wavefront (LDS executes a wave's operations in
+// issue order; this keeps the compiler from moving accesses across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// DPP quad permutations: lane i reads lane i^1 / i^2 of its quad.
+constexpr int kQuadXor1 = 0xB1; // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E; // quad_perm [2,3,0,1]
+
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Radix-4 step across the four lanes of a quad, for each of the Q values a
+// lane holds.  Forward (S = -1): lane q holds Y_q[k] and ends with
+// X[k + Q p(q)] = sum_q' Y_q'[k] W_4^{S q' p}, p(q) = {0, 2, 1, 3}[q]:
+//   stage 1 (lanes q, q^2): u = s1 own + partner, s1 = -1 for q >= 2;
+//   lane 3 multiplies by W_4^S (= S i);
+//   stage 2 (lanes q, q^1): X = s2 own + partner, s2 = -1 for odd q.
+// Reverse (S = +1) runs the same steps in the opposite order so that lane q
+// ends with Z_q[k] = sum_p X[k + Q p] W_4^{S q p}.
+template <int Q, int S, typename T>
+__device__ __forceinline__ void quad_radix4(T *xr, T *xi, int q)
+{
+    const T s1 = (q & 2) ? T(-1) : T(1);
+    const T s2 = (q & 1) ? T(-1) : T(1);
+    // twist on lane 3: (re, im) -> (-S im, S re), as t = c0 (re, im) + c1 (-im, re)
+    const T c0 = (q == 3) ? T(0) : T(1);
+    const T c1 = (q == 3) ? T(S) : T(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        T ar = xr[k], ai = xi[k];
+        if constexpr (S < 0) {
+            T pr = quad_swap<kQuadXor2>(ar), pi = quad_swap<kQuadXor2>(ai);
+            ar = s1 * ar + pr;
+            ai = s1 * ai + pi;
+        } else {
+            T pr = quad_swap<kQuadXor1>(ar), pi = quad_swap<kQuadXor1>(ai);
+            ar = s2 * ar + pr;
+            ai = s2 * ai + pi;
+        }
+        T tr = c0 * ar - c1 * ai;
+        T ti = c0 * ai + c1 * ar;
+        if constexpr (S < 0) {
+            T pr = quad_swap<kQuadXor1>(tr), pi = quad_swap<kQuadXor1>(ti);
+            xr[k] = s2 * tr + pr;
+            xi[k] = s2 * ti + pi;
+        } else {
+            T pr = quad_swap<kQuadXor2>(tr), pi = quad_swap<kQuadXor2>(ti);
+            xr[k] = s1 * tr + pr;
+            xi[k] = s1 * ti + pi;
+        }
+    }
+}
+
+// Per k: forward radix-4 across the quad, multiply by V at the lane's own
+// frequency k + Q p(q), reverse radix-4; V is read one value at a time.
+template <typename T>
+__device__ __forceinline__ void quad_radix4_v_one(T &xr, T &xi, T v, T s1, T s2, T c0, T c1)
+{
+    T ar = xr, ai = xi;
+    T pr = quad_swap<kQuadXor2>(ar), pi = quad_swap<kQuadXor2>(ai);
+    ar = s1 * ar + pr;
+    ai = s1 * ai + pi;
+    T tr = c0 * ar + c1 * ai; // lane 3: -i (ar + i ai) = (ai, -ar)
+    T ti = c0 * ai - c1 * ar;
+    pr = quad_swap<kQuadXor1>(tr);
+    pi = quad_swap<kQuadXor1>(ti);
+    ar = (s2 * tr + pr) * v;
+    ai = (s2 * ti + pi) * v;
+    pr = quad_swap<kQuadXor1>(ar);
+    pi = quad_swap<kQuadXor1>(ai);
+    ar = s2 * ar + pr;
+    ai = s2 * ai + pi;
+    tr = c0 * ar - c1 * ai; // lane 3: +i (ar + i ai) = (-ai, ar)
+    ti = c0 * ai + c1 * ar;
+    pr = quad_swap<kQuadXor2>(tr);
+    pi = quad_swap<kQuadXor2>(ti);
+    xr = s1 * tr + pr;
+    xi = s1 * ti + pi;
+}
+
+// Per k: forward radix-4 across the quad, multiply by V at the lane's own
+// frequency k + Q p(q), reverse radix-4.  V is read in groups of G values,
+// one group ahead of its use (the memory barrier keeps the compiler from
+// hoisting every load to the top, which would cost 2 Q registers).
+template <int Q, typename T>
+__device__ __forceinline__ void quad_radix4_v(T *xr, T *xi, int q, const T *__restrict__ vrow)
+{
+    constexpr int G = (Q % 6 == 0) ? 6 : ((Q % 4 == 0) ? 4 : ((Q % 5 == 0) ? 5 : Q));
+    const T s1 = (q & 2) ? T(-1) : T(1);
+    const T s2 = (q & 1) ? T(-1) : T(1);
+    const T c0 = (q == 3) ? T(0) : T(1);
+    const T c1 = (q == 3) ? T(1) : T(0);
+    T vb[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) vb[j] = vrow[j];
+#pragma unroll
+    for (int g0 = 0; g0 < Q; g0 += G) {
+        T vn[G];
+        if (g0 + G < Q) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) vn[j] = vrow[g0 + G + j];
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) quad_radix4_v_one(xr[g0 + j], xi[g0 + j], vb[j], s1, s2, c0, c1);
+        asm volatile("" ::: "memory");
+        if (g0 + G < Q) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) vb[j] = vn[j];
+        }
+    }
+}
+
+// x[k] *= W_L^{S q k} for k < Q, twiddles built in FP64 by a recurrence from
+// exp(-2 pi i q / L), re-anchored from the exact table every 8 steps.
+template <int Q, int S, typename T>
+__device__ __forceinline__ void quad_twiddle(T *xr, T *xi, int q, int L,
+                                             const double2 *__restrict__ tw64)
+{
+    const double2 b = tw64[q];
+    const double br = b.x, bi = (S < 0) ? b.y : -b.y;
+    double wr = 1.0, wi = 0.0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+        if (k % 8 == 0) {
+            const double2 a = tw64[(q * k) % L];
+            wr = a.x;
+            wi = (S < 0) ? a.y : -a.y;
+        } else {
+            double nr = wr * br - wi * bi;
+            wi = wr * bi + wi * br;
+            wr = nr;
+        }
+        T a = xr[k], c = xi[k];
+        T twr = T(wr), twi = T(wi);
+        xr[k] = a * twr - c * twi;
+        xi[k] = a * twi + c * twr;
+    }
+}
+
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int XQ>
+__device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t,
+                                           cx<T> *__restrict__ S, const T *__restrict__ V,
+                                           cx<T> *__restrict__ psi, long long band0, int nb)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *rowbuf = plane + g.nxo * g.ldy;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int L1x = CX1 ? CX1 : g.L1x, L2x = CX2 ? CX2 : g.L2x;
+    const int L1y = CY1 ? CY1 : g.L1y, L2y = CY2 ? CY2 : g.L2y;
+    const int N1 = g.N1, N2 = g.N2, nxo = g.nxo, ldy = g.ldy;
+    const int RB = g.rb, RL = g.rl;
+    cx<T> *rows = plane + nxo * ldy + wave * RB * RL;
 
     // XCD-aware order: consecutive workgroups go to different XCDs, so give
     // each XCD a contiguous run of (z, band) pairs; the bands of one z then
@@ -239,8 +418,6 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
     if ((nblk & 7) == 0) jb = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
     const int z = jb / nb, bl = jb - z * nb;
 
-    const int N1 = g.N1, N2 = g.N2, nxo = g.nxo, ldy = g.ldy, ldx = g.ldx;
-    const int L1x = g.L1x, L2x = g.L2x, L1y = g.L1y, L2y = g.L2y;
     const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
     const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
     cx<T> *Sz = S + ((long long)bl * g.N3 + z) * g.nst;
@@ -248,20 +425,22 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
     const T *Vz = V ? V + (long long)z * N2 * N1 : nullptr;
 
     if (MODE != MODE_R2G) {
-        for (int e = tid; e < nxo * ldy; e += nthr) plane[e] = mk<T>(T(0), T(0));
-        __syncthreads();
         for (int s = tid; s < g.nst; s += nthr) plane[t.slot_info[s].w] = Sz[s];
         __syncthreads();
-        // y forward, stage A
-        with_codelet(L1y, [&](auto RC) {
+        // y forward, stage A (lanes along columns)
+        with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L2y; task += nthr) {
-                const int hc = task / L2y, n2 = task - hc * L2y;
+                const int n2 = task / nxo, hc = task - n2 * nxo;
+                const int2 ci = t.cols[hc];
                 cx<T> *col = plane + hc * ldy + n2;
                 T xr[R], xi[R];
 #pragma unroll
                 for (int n1 = 0; n1 < R; ++n1) {
-                    cx<T> v = col[L2y * n1];
+                    int rel = n2 + L2y * n1 - ci.x;
+                    if (rel < 0) rel += N2;
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (rel < ci.y) v = col[L2y * n1];
                     xr[n1] = v.x;
                     xi[n1] = v.y;
                 }
@@ -272,11 +451,11 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
             }
         });
         __syncthreads();
-        // y forward, stage B
-        with_codelet(L2y, [&](auto RC) {
+        // y forward, stage B (lanes along columns)
+        with_size<CY2>(L2y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L1y; task += nthr) {
-                const int hc = task / L1y, k1 = task - hc * L1y;
+                const int k1 = task / nxo, hc = task - k1 * nxo;
                 cx<T> *col = plane + hc * ldy + L2y * k1;
                 T xr[R], xi[R];
 #pragma unroll
@@ -293,115 +472,177 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
         __syncthreads();
     }
 
-    // x pass, in batches of rows
-    for (int y0 = 0; y0 < N2; y0 += g.rows) {
-        const int nr = min(g.rows, N2 - y0);
-        if (MODE != MODE_R2G) {
-            with_codelet(L1x, [&](auto RC) {
-                constexpr int R = decltype(RC)::value;
-                for (int task = tid; task < nr * L2x; task += nthr) {
-                    const int r = task / L2x, n2 = task - r * L2x;
-                    const int y = y0 + r;
-                    const int yp = L2y * (y % L1y) + y / L1y;
-                    T xr[R], xi[R];
+    if constexpr (XQ > 0) {
+        // x pass, one quad of lanes per row: N1 = 4 XQ, lane q of the quad
+        // holds x[q + 4 m]; an XQ-point register DFT, twiddles, and the
+        // radix-4 step across the quad give X[k + XQ p(q)] on lane q; after
+        // the potential the steps run in reverse.
+        const int q = tid & 3, y = tid >> 2;
+        const double2 *tw64 = t.twx64;
+        if (y < N2) {
+            const int yp = L2y * (y % L1y) + y / L1y;
+            T xr[XQ], xi[XQ];
+            if (MODE != MODE_R2G) {
 #pragma unroll
-                    for (int n1 = 0; n1 < R; ++n1) {
-                        int hc = n2 + L2x * n1 - g.hmin_mod;
-                        if (hc < 0) hc += N1;
-                        cx<T> v = mk<T>(T(0), T(0));
-                        if (hc < nxo) v = plane[hc * ldy + yp];
-                        xr[n1] = v.x;
-                        xi[n1] = v.y;
-                    }
-                    Dft<R, -1, T>::run(xr, xi);
-                    twiddle<R, -1, T>(xr, xi, n2, twx);
-                    cx<T> *row = rowbuf + r * ldx + n2;
-#pragma unroll
-                    for (int k1 = 0; k1 < R; ++k1) row[L2x * k1] = mk<T>(xr[k1], xi[k1]);
+                for (int m = 0; m < XQ; ++m) {
+                    int hc = q + 4 * m - g.hmin_mod;
+                    if (hc < 0) hc += N1;
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (hc < nxo) v = plane[hc * ldy + yp];
+                    xr[m] = v.x;
+                    xi[m] = v.y;
                 }
-            });
-            __syncthreads();
+                Dft<XQ, -1, T>::run(xr, xi);
+                quad_twiddle<XQ, -1, T>(xr, xi, q, N1, tw64);
+                if (MODE == MODE_G2R) quad_radix4<XQ, -1, T>(xr, xi, q);
+            }
+            const int pq = ((q & 1) << 1) | (q >> 1); // p(q) = {0, 2, 1, 3}
+            if (MODE == MODE_G2R) {
+                cx<T> *dst = psiz + (long long)y * N1 + XQ * pq;
+#pragma unroll
+                for (int k = 0; k < XQ; ++k) dst[k] = mk<T>(xr[k], xi[k]);
+            } else {
+                if (MODE == MODE_APPLY) {
+                    quad_radix4_v<XQ, T>(xr, xi, q, Vz + (long long)y * N1 + XQ * pq);
+                } else {
+                    const cx<T> *src = psiz + (long long)y * N1 + XQ * pq;
+#pragma unroll
+                    for (int k = 0; k < XQ; ++k) {
+                        cx<T> v = src[k];
+                        xr[k] = v.x;
+                        xi[k] = v.y;
+                    }
+                    quad_radix4<XQ, +1, T>(xr, xi, q);
+                }
+                quad_twiddle<XQ, +1, T>(xr, xi, q, N1, tw64);
+                Dft<XQ, +1, T>::run(xr, xi);
+#pragma unroll
+                for (int m = 0; m < XQ; ++m) {
+                    int hc = q + 4 * m - g.hmin_mod;
+                    if (hc < 0) hc += N1;
+                    if (hc < nxo) plane[hc * ldy + yp] = mk<T>(xr[m], xi[m]);
+                }
+            }
         }
-        with_codelet(L2x, [&](auto RC) {
-            constexpr int R = decltype(RC)::value;
-            for (int task = tid; task < nr * L1x; task += nthr) {
-                const int r = task / L1x, k1 = task - r * L1x;
-                const int y = y0 + r;
-                cx<T> *row = rowbuf + r * ldx + L2x * k1;
-                T xr[R], xi[R];
-                if (MODE == MODE_R2G) {
-                    const cx<T> *src = psiz + (long long)y * N1 + k1;
+    } else if (wave < g.xw) {
+    // x pass: waves 0 .. xw-1 each own a contiguous block of rows and a private
+    // row buffer of rb rows; a stage needing more than 64 tasks loops
+        const int rpw = (N2 + g.xw - 1) / g.xw;
+        const int ybeg = wave * rpw, yend = min(N2, ybeg + rpw);
+        for (int y0 = ybeg; y0 < yend; y0 += RB) {
+            const int nr = min(RB, yend - y0);
+            if (MODE != MODE_R2G) {
+                with_size<CX1>(L1x, [&](auto RC) {
+                    constexpr int R = decltype(RC)::value;
+                    for (int task = lane; task < nr * L2x; task += 64) {
+                        const int r = task / L2x, n2 = task - r * L2x;
+                        const int y = y0 + r;
+                        const int yp = L2y * (y % L1y) + y / L1y;
+                        T xr[R], xi[R];
 #pragma unroll
-                    for (int k2 = 0; k2 < R; ++k2) {
-                        cx<T> v = src[L1x * k2];
-                        xr[k2] = v.x;
-                        xi[k2] = v.y;
+                        for (int n1 = 0; n1 < R; ++n1) {
+                            int hc = n2 + L2x * n1 - g.hmin_mod;
+                            if (hc < 0) hc += N1;
+                            cx<T> v = mk<T>(T(0), T(0));
+                            if (hc < nxo) v = plane[hc * ldy + yp];
+                            xr[n1] = v.x;
+                            xi[n1] = v.y;
+                        }
+                        Dft<R, -1, T>::run(xr, xi);
+                        twiddle<R, -1, T>(xr, xi, n2, twx);
+                        cx<T> *row = rows + r * RL + n2;
+#pragma unroll
+                        for (int k1 = 0; k1 < R; ++k1) row[(L2x + 1) * k1] = mk<T>(xr[k1], xi[k1]);
                     }
-                } else {
-#pragma unroll
-                    for (int n2 = 0; n2 < R; ++n2) {
-                        cx<T> v = row[n2];
-                        xr[n2] = v.x;
-                        xi[n2] = v.y;
-                    }
-                    Dft<R, -1, T>::run(xr, xi);
-                }
-                if (MODE == MODE_G2R) {
-                    cx<T> *dst = psiz + (long long)y * N1 + k1;
-#pragma unroll
-                    for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
-                } else {
+                });
+                wave_sync();
+            }
+            with_size<CX2>(L2x, [&](auto RC) {
+                constexpr int R = decltype(RC)::value;
+                for (int task = lane; task < nr * L1x; task += 64) {
+                    const int r = task / L1x, k1 = task - r * L1x;
+                    const int y = y0 + r;
+                    cx<T> *row = rows + r * RL + (L2x + 1) * k1;
+                    T xr[R], xi[R];
+                    T vv[R];
                     if (MODE == MODE_APPLY) {
                         const T *vrow = Vz + (long long)y * N1 + k1;
 #pragma unroll
+                        for (int k2 = 0; k2 < R; ++k2) vv[k2] = vrow[L1x * k2];
+                    }
+                    if (MODE == MODE_R2G) {
+                        const cx<T> *src = psiz + (long long)y * N1 + k1;
+#pragma unroll
                         for (int k2 = 0; k2 < R; ++k2) {
-                            T v = vrow[L1x * k2];
-                            xr[k2] *= v;
-                            xi[k2] *= v;
+                            cx<T> v = src[L1x * k2];
+                            xr[k2] = v.x;
+                            xi[k2] = v.y;
                         }
+                    } else {
+#pragma unroll
+                        for (int n2 = 0; n2 < R; ++n2) {
+                            cx<T> v = row[n2];
+                            xr[n2] = v.x;
+                            xi[n2] = v.y;
+                        }
+                        Dft<R, -1, T>::run(xr, xi);
                     }
-                    Dft<R, +1, T>::run(xr, xi);
+                    if (MODE == MODE_G2R) {
+                        cx<T> *dst = psiz + (long long)y * N1 + k1;
 #pragma unroll
-                    for (int n2 = 0; n2 < R; ++n2) row[n2] = mk<T>(xr[n2], xi[n2]);
-                }
-            }
-        });
-        __syncthreads();
-        if (MODE != MODE_G2R) {
-            with_codelet(L1x, [&](auto RC) {
-                constexpr int R = decltype(RC)::value;
-                for (int task = tid; task < nr * L2x; task += nthr) {
-                    const int r = task / L2x, n2 = task - r * L2x;
-                    const int y = y0 + r;
-                    const int yp = L2y * (y % L1y) + y / L1y;
-                    const cx<T> *row = rowbuf + r * ldx + n2;
-                    T xr[R], xi[R];
+                        for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
+                    } else {
+                        if (MODE == MODE_APPLY) {
 #pragma unroll
-                    for (int k1 = 0; k1 < R; ++k1) {
-                        cx<T> v = row[L2x * k1];
-                        xr[k1] = v.x;
-                        xi[k1] = v.y;
-                    }
-                    twiddle<R, +1, T>(xr, xi, n2, twx);
-                    Dft<R, +1, T>::run(xr, xi);
+                            for (int k2 = 0; k2 < R; ++k2) {
+                                xr[k2] *= vv[k2];
+                                xi[k2] *= vv[k2];
+                            }
+                        }
+                        Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
-                    for (int n1 = 0; n1 < R; ++n1) {
-                        int hc = n2 + L2x * n1 - g.hmin_mod;
-                        if (hc < 0) hc += N1;
-                        if (hc < nxo) plane[hc * ldy + yp] = mk<T>(xr[n1], xi[n1]);
+                        for (int n2 = 0; n2 < R; ++n2) row[n2] = mk<T>(xr[n2], xi[n2]);
                     }
                 }
             });
-            __syncthreads();
+            wave_sync();
+            if (MODE != MODE_G2R) {
+                with_size<CX1>(L1x, [&](auto RC) {
+                    constexpr int R = decltype(RC)::value;
+                    for (int task = lane; task < nr * L2x; task += 64) {
+                        const int r = task / L2x, n2 = task - r * L2x;
+                        const int y = y0 + r;
+                        const int yp = L2y * (y % L1y) + y / L1y;
+                        const cx<T> *row = rows + r * RL + n2;
+                        T xr[R], xi[R];
+#pragma unroll
+                        for (int k1 = 0; k1 < R; ++k1) {
+                            cx<T> v = row[(L2x + 1) * k1];
+                            xr[k1] = v.x;
+                            xi[k1] = v.y;
+                        }
+                        twiddle<R, +1, T>(xr, xi, n2, twx);
+                        Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+                        for (int n1 = 0; n1 < R; ++n1) {
+                            int hc = n2 + L2x * n1 - g.hmin_mod;
+                            if (hc < 0) hc += N1;
+                            if (hc < nxo) plane[hc * ldy + yp] = mk<T>(xr[n1], xi[n1]);
+                        }
+                    }
+                });
+                wave_sync();
+            }
         }
     }
     if (MODE == MODE_G2R) return;
+    __syncthreads();
 
-    // y reverse, stage B'
-    with_codelet(L2y, [&](auto RC) {
+    // y reverse, stage B' (lanes along columns)
+    with_size<CY2>(L2y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L1y; task += nthr) {
-            const int hc = task / L1y, k1 = task - hc * L1y;
+            const int k1 = task / nxo, hc = task - k1 * nxo;
             cx<T> *col = plane + hc * ldy + L2y * k1;
             T xr[R], xi[R];
 #pragma unroll
@@ -416,11 +657,12 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
         }
     });
     __syncthreads();
-    // y reverse, stage A'
-    with_codelet(L1y, [&](auto RC) {
+    // y reverse, stage A' (lanes along columns): only stick positions are kept
+    with_size<CY1>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
-            const int hc = task / L2y, n2 = task - hc * L2y;
+            const int n2 = task / nxo, hc = task - n2 * nxo;
+            const int2 ci = t.cols[hc];
             cx<T> *col = plane + hc * ldy + n2;
             T xr[R], xi[R];
 #pragma unroll
@@ -432,11 +674,34 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *_
             twiddle<R, +1, T>(xr, xi, n2, twy);
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
-            for (int n1 = 0; n1 < R; ++n1) col[L2y * n1] = mk<T>(xr[n1], xi[n1]);
+            for (int n1 = 0; n1 < R; ++n1) {
+                int rel = n2 + L2y * n1 - ci.x;
+                if (rel < 0) rel += N2;
+                if (rel < ci.y) col[L2y * n1] = mk<T>(xr[n1], xi[n1]);
+            }
         }
     });
     __syncthreads();
     for (int s = tid; s < g.nst; s += nthr) Sz[s] = plane[t.slot_info[s].w];
+}
+
+// LDS row-buffer variant (any split), up to 512 threads.
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2>
+__global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *__restrict__ S,
+                                               const T *__restrict__ V,
+                                               cx<T> *__restrict__ psi, long long band0, int nb)
+{
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, 0>(g, t, S, V, psi, band0, nb);
+}
+
+// Quad variant: no row buffer, so the occupied plane is the only LDS and two
+// workgroups fit on a CU even in FP64; 3 waves per SIMD bound the registers.
+template <typename T, int MODE, int XQ, int CY1, int CY2>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3)))
+void k_plane_quad(Geometry g, DevTables t, cx<T> *__restrict__ S, const T *__restrict__ V,
+                  cx<T> *__restrict__ psi, long long band0, int nb)
+{
+    plane_body<T, MODE, 0, 0, CY1, CY2, XQ>(g, t, S, V, psi, band0, nb);
 }
 
 // ------------------------------------------------------------ launchers
@@ -477,17 +742,64 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S
     return hipGetLastError();
 }
 
+template <typename T, int MODE, int X1, int X2, int Y1, int Y2>
+static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, void *S, const void *V,
+                                     void *psi, int64_t band0, int nb, int threads, int lds,
+                                     hipStream_t st)
+{
+    auto kern = k_plane<T, MODE, X1, X2, Y1, Y2>;
+    hipError_t e = allow_lds(kern, (size_t)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds, st, g, t,
+                       reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                       reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE, int XQ, int Y1, int Y2>
+static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, void *S, const void *V,
+                                    void *psi, int64_t band0, int nb, int threads, int lds,
+                                    hipStream_t st)
+{
+    auto kern = k_plane_quad<T, MODE, XQ, Y1, Y2>;
+    hipError_t e = allow_lds(kern, (size_t)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds, st, g, t,
+                       reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                       reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
+    return hipGetLastError();
+}
+
+// Specialised line splits for the common grids; any other split runs the same
+// kernel with runtime sizes.
 template <typename T, int MODE>
 static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void *S, const void *V,
                                     void *psi, int64_t band0, int nb, int threads, int lds,
                                     hipStream_t st)
 {
-    hipError_t e = allow_lds(k_plane<T, MODE>, (size_t)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_plane<T, MODE>), dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds,
-                       st, g, t, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
-                       reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
-    return hipGetLastError();
+    if (g.xq) {
+#define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
+        if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
+            return launch_plane_quad<T, MODE, XQ, Y1, Y2>(g, t, S, V, psi, band0, nb, threads,    \
+                                                           lds, st);
+        VLOC_QUAD_CASE(24, 8, 12)
+        VLOC_QUAD_CASE(6, 4, 6)
+        VLOC_QUAD_CASE(18, 8, 12)
+        VLOC_QUAD_CASE(20, 8, 10)
+#undef VLOC_QUAD_CASE
+        return hipErrorInvalidValue;
+    }
+#define VLOC_PLANE_CASE(X1, X2, Y1, Y2)                                                            \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2)                                 \
+        return launch_plane_sized<T, MODE, X1, X2, Y1, Y2>(g, t, S, V, psi, band0, nb, threads,   \
+                                                           lds, st);
+    VLOC_PLANE_CASE(8, 12, 8, 12)
+    VLOC_PLANE_CASE(4, 6, 4, 6)
+    VLOC_PLANE_CASE(8, 16, 8, 16)
+    VLOC_PLANE_CASE(8, 10, 8, 10)
+    VLOC_PLANE_CASE(8, 9, 8, 12)
+#undef VLOC_PLANE_CASE
+    return launch_plane_sized<T, MODE, 0, 0, 0, 0>(g, t, S, V, psi, band0, nb, threads, lds, st);
 }
 
 template <typename T>

@@ -11,7 +11,9 @@ enum PlaneMode { MODE_APPLY = 0, MODE_G2R = 1, MODE_R2G = 2 };
 struct DevTables {
     const int4 *slot_info;  // per slot: {offset, count, lmin mod N3, plane position}
     const int2 *groups;     // per group: {first slot, number of sticks}
+    const int2 *cols;       // per occupied x-plane: {first k mod N2, number of k}
     const void *twx, *twy, *twz; // exp(-2 pi i j / L), complex of the plan precision
+    const double2 *twx64;        // exp(-2 pi i j / N1) in FP64 (quad x pass)
 };
 
 struct Geometry {
@@ -20,7 +22,10 @@ struct Geometry {
     int nxo;        // occupied x-planes
     int hmin_mod;   // hmin mod N1
     int ldy, ldx, ldz;
-    int rows;       // x rows per batch in the plane kernel
+    int rows;       // unused (kept for layout reporting)
+    int rb, rl;     // x rows per wavefront batch, padded row length in the plane kernel
+    int xw;         // wavefronts taking part in the x pass
+    int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
     int nst, npw, ngroups;
     int group_cap;  // most sticks in one group
     double inv_n;   // 1 / (N1 N2 N3)

@@ -9,6 +9,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
@@ -110,8 +111,11 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     }
     if (p.opt.sticks_per_group < 0 || p.opt.sticks_per_group > 64 || p.opt.band_chunk < 0 ||
         p.opt.plane_rows < 0 || p.opt.plane_threads < 0 || p.opt.plane_threads > 512 ||
-        (p.opt.plane_threads % 64) != 0) {
-        err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64)";
+        (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
+        p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 2) {
+        err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64, "
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..2)";
         return VLOC_E_INVALID;
     }
     for (int i = 0; i < 3; ++i) {
@@ -256,32 +260,116 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         for (int32_t s : members[g]) p.stick_of_slot.push_back(s);
     }
 
-    // ---- plane kernel sizing: plane (nxo x N2) plus a batch of full x rows
+    // ---- plane kernel sizing: the occupied plane (nxo x N2, column stride
+    // ldy) plus, per wavefront, a batch of rb full x rows of padded length rl
     p.ldy = grid[1] + 1;
     p.ldx = grid[0] + 1;
     const int64_t plane_bytes = (int64_t)p.nxo * p.ldy * es;
-    const int64_t row_bytes = (int64_t)p.ldx * es;
     const int64_t lds_max = 160 * 1024;
-    p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads : 512;
-    int xtasks = std::max(p.sx.L1, p.sx.L2);
-    int rows = p.opt.plane_rows;
-    if (rows == 0) {
-        rows = std::max(1, p.plane_threads / xtasks);
-        // a smaller batch that leaves room for two workgroups per CU wins if it
-        // still keeps half the threads busy
-        int64_t two = (lds_max / 2 - plane_bytes) / row_bytes;
-        if (two * xtasks >= p.plane_threads / 2) rows = (int)std::min<int64_t>(rows, two);
-    }
-    rows = std::min(rows, grid[1]);
-    if (plane_bytes + rows * row_bytes > lds_max) {
-        rows = (int)((lds_max - plane_bytes) / row_bytes);
-        if (rows < 1) {
-            err = "occupied plane does not fit in LDS";
-            return VLOC_E_GRID;
+    p.plane_rl = p.sx.L1 * (p.sx.L2 + 1);
+    const int nwaves = (p.opt.plane_threads ? p.opt.plane_threads : 512) / 64;
+    p.plane_threads = nwaves * 64;
+    // Choose (x waves, rows per batch) by an estimate of the plane time in
+    // wave instructions: a stage with more than 64 tasks costs whole extra
+    // rounds.  The y pass runs on all 4 SIMDs; the x pass on min(4, xw) of them
+    // and no faster than its slowest wave, with a latency charge of 1/(2 xw);
+    // the sum is divided by the workgroups that fit on a CU (LDS-bound, <= 2).
+    auto log2i = [](int v) { double l = 0; while (v > 1) { v >>= 1; l += 1; } return l; };
+    const double cA = 3.0 * p.sx.L1 * log2i(p.sx.L1) + 4.0 * (p.sx.L1 - 1) + 20.0;
+    const double cB = 6.0 * p.sx.L2 * log2i(p.sx.L2) + 2.0 * p.sx.L2 + 30.0;
+    const double cAy = 3.0 * p.sy.L1 * log2i(p.sy.L1) + 4.0 * (p.sy.L1 - 1) + 20.0;
+    const double cBy = 3.0 * p.sy.L2 * log2i(p.sy.L2) + 30.0;
+    const int N2 = grid[1];
+    const double ycost = 2.0 * (((int64_t)p.nxo * p.sy.L2 + 63) / 64 * cAy +
+                                ((int64_t)p.nxo * p.sy.L1 + 63) / 64 * cBy);
+    double best = 1e300;
+    int best_xw = 0, best_rb = 0;
+    for (int xw = 1; xw <= nwaves; ++xw) {
+        if (p.opt.plane_xwaves && xw != p.opt.plane_xwaves) continue;
+        const int rpw = (N2 + xw - 1) / xw;
+        for (int rb = 1; rb <= rpw; ++rb) {
+            if (p.opt.plane_rows && rb != std::min<int>(p.opt.plane_rows, rpw)) continue;
+            const int64_t lds = plane_bytes + (int64_t)xw * rb * p.plane_rl * es;
+            if (lds > lds_max) break;
+            double total = 0, slowest = 0;
+            for (int w = 0; w < xw; ++w) {
+                int rows = std::min(rpw, std::max(0, N2 - w * rpw));
+                double c = 0;
+                for (int y = 0; y < rows; y += rb) {
+                    int nr = std::min(rb, rows - y);
+                    c += 2 * cA * ((nr * p.sx.L2 + 63) / 64) + cB * ((nr * p.sx.L1 + 63) / 64);
+                }
+                total += c;
+                slowest = std::max(slowest, c);
+            }
+            const int nwg = (int)std::min<int64_t>(2, lds_max / lds);
+            double tx = std::max(total / std::min(4, xw), slowest) * (1.0 + 0.5 / xw);
+            double t = (ycost / 4.0 + tx) / nwg;
+            if (t < best - 1e-9 || (std::abs(t - best) <= 1e-9 && xw > best_xw)) {
+                best = t;
+                best_xw = xw;
+                best_rb = rb;
+            }
         }
     }
-    p.plane_rows = rows;
-    p.plane_lds = (int32_t)(plane_bytes + rows * row_bytes);
+    if (best_xw == 0) {
+        err = "occupied plane does not fit in LDS";
+        return VLOC_E_GRID;
+    }
+    p.plane_xw = best_xw;
+    p.plane_rb = best_rb;
+    p.plane_rows = best_rb;
+    p.plane_lds = (int32_t)(plane_bytes + (int64_t)best_xw * best_rb * p.plane_rl * es);
+    // Quad x pass: one lane quad per row holds a whole row in registers, so
+    // the occupied plane is the only LDS.  Compiled for N1 = 4 xq with
+    // xq in {6, 18, 20, 24} and the y split each goes with.
+    {
+        int xq = (grid[0] % 4 == 0) ? grid[0] / 4 : 0;
+        bool have = (xq == 24 && p.sy.L1 == 8 && p.sy.L2 == 12) ||
+                    (xq == 6 && p.sy.L1 == 4 && p.sy.L2 == 6) ||
+                    (xq == 18 && p.sy.L1 == 8 && p.sy.L2 == 12) ||
+                    (xq == 20 && p.sy.L1 == 8 && p.sy.L2 == 10);
+        int qthreads = ((4 * grid[1] + 63) / 64) * 64;
+        bool fits = have && qthreads <= 512 && plane_bytes <= lds_max;
+        // measured slower than the row buffers in both precisions at 96^3, so
+        // only used when asked for
+        bool want = p.opt.plane_xmode == 2;
+        if (p.opt.plane_xmode == 2 && !fits) {
+            err = "quad x pass not available for this grid";
+            return VLOC_E_INVALID;
+        }
+        if (want && fits) {
+            p.plane_xq = xq;
+            p.plane_threads = p.opt.plane_threads ? std::max<int>(p.opt.plane_threads, qthreads)
+                                                  : qthreads;
+            p.plane_xw = 0;
+            p.plane_rb = 1;
+            p.plane_rows = 0;
+            p.plane_lds = (int32_t)plane_bytes;
+        }
+    }
+    // per occupied x-plane: first k (mod N2) and number of k on sticks
+    p.col_kmin.assign(p.nxo, 0);
+    p.col_kcnt.assign(p.nxo, 0);
+    {
+        std::vector<int32_t> kmin(p.nxo, INT32_MAX), kmax(p.nxo, INT32_MIN);
+        for (const Stick &s : p.sticks) {
+            int hc = s.h - p.hmin;
+            kmin[hc] = std::min(kmin[hc], s.k);
+            kmax[hc] = std::max(kmax[hc], s.k);
+        }
+        std::vector<int32_t> seen(p.nxo, 0);
+        for (const Stick &s : p.sticks) seen[s.h - p.hmin]++;
+        for (int hc = 0; hc < p.nxo; ++hc) {
+            if (!seen[hc]) continue;
+            if (kmax[hc] - kmin[hc] + 1 != seen[hc]) {
+                err = "internal: k range of an x-plane has holes";
+                return VLOC_E_SPHERE;
+            }
+            p.col_kmin[hc] = ((kmin[hc] % grid[1]) + grid[1]) % grid[1];
+            p.col_kcnt[hc] = seen[hc];
+        }
+    }
 
     // ---- band chunk: stick buffer of one chunk <= 128 MiB (stays in the 256 MB
     // memory-side cache between the three kernels)

@@ -43,6 +43,10 @@ struct HostPlan {
     int32_t plane_lds = 0;    // bytes of LDS per plane workgroup
     int32_t stick_threads = 0;
     int32_t ldy = 0, ldx = 0, ldz = 0; // LDS line strides (complex elements)
+    int32_t plane_rb = 0, plane_rl = 0; // x rows per wave batch, padded row length
+    int32_t plane_xw = 0;               // wavefronts running the x pass
+    int32_t plane_xq = 0;               // > 0: quad x pass, N1 = 4 plane_xq
+    std::vector<int32_t> col_kmin, col_kcnt; // per occupied x-plane k range
 
     int64_t npw() const { return (int64_t)hkl.size() / 3; }
     int64_t nst() const { return (int64_t)sticks.size(); }

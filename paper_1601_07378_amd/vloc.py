@@ -46,7 +46,8 @@ class VlocError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("deal", ctypes.c_int32),
                 ("sticks_per_group", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
-                ("plane_rows", ctypes.c_int32), ("plane_threads", ctypes.c_int32)]
+                ("plane_rows", ctypes.c_int32), ("plane_threads", ctypes.c_int32),
+                ("plane_xwaves", ctypes.c_int32), ("plane_xmode", ctypes.c_int32)]
 
 
 _lib = None
@@ -115,7 +116,8 @@ class Plan:
 
     def __init__(self, grid, cell, ecut: float, k=(0.0, 0.0, 0.0), precision: str = "f64",
                  deal: str = "greedy", sticks_per_group: int = 0, band_chunk: int = 0,
-                 plane_rows: int = 0, plane_threads: int = 0):
+                 plane_rows: int = 0, plane_threads: int = 0, plane_xwaves: int = 0,
+                 plane_xmode: int = 0):
         self._h = ctypes.c_void_p()
         g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32).reshape(3))
         c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
@@ -123,7 +125,8 @@ class Plan:
         if precision not in ("f64", "f32"):
             raise ValueError("precision must be 'f64' or 'f32'")
         opt = Options(VLOC_F64 if precision == "f64" else VLOC_F32, DEALS[deal],
-                      sticks_per_group, band_chunk, plane_rows, plane_threads)
+                      sticks_per_group, band_chunk, plane_rows, plane_threads, plane_xwaves,
+                      plane_xmode)
         check(lib().vloc_plan_create_ex(ctypes.byref(self._h), _i32(g), _f64(c), float(ecut),
                                         _f64(kk), ctypes.byref(opt)))
         self.grid = tuple(int(x) for x in g)
@@ -170,10 +173,11 @@ class Plan:
         return out
 
     def layout(self) -> dict:
-        v = np.empty(12, dtype=np.int32)
+        v = np.empty(14, dtype=np.int32)
         check(lib().vloc_plan_layout(self._h, _i32(v)))
         keys = ["L1x", "L2x", "L1y", "L2y", "L1z", "L2z", "sticks_per_group", "band_chunk",
-                "plane_rows", "plane_threads", "plane_lds_bytes", "nxo"]
+                "plane_rows", "plane_threads", "plane_lds_bytes", "nxo", "plane_xwaves",
+                "plane_xmode"]
         return dict(zip(keys, (int(x) for x in v)))
 
     # ---- per-kernel timing (HIP events around each launch on the plan stream)

@@ -191,3 +191,34 @@ def test_apply_f32_error(name, grid, cell, ecut, k, nb):
     total = relerr_per_band(got, oracle.apply(grid, cell, ecut, k, c, V))
     print(name, "f32 arithmetic err", arith.max(), "total err", total.max())
     assert arith.max() <= TOL32 and total.max() <= TOL32
+
+
+# ------------------------------------------- plane-kernel x-pass variants
+
+XMODE_CASES = [
+    ("c1", (24, 24, 24), synth.cubic_cell(), 18.0, (0, 0, 0), 3),
+    ("ortho_k", (72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0.25, 0.0), 2),
+    ("m0_80", (80, 80, 80), synth.cubic_cell(), 206.5, (0, 0, 0), 2),
+]
+
+
+@pytest.mark.parametrize("xmode", [1, 2])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,grid,cell,ecut,k,nb", XMODE_CASES)
+def test_plane_xmodes_vs_oracle(xmode, precision, name, grid, cell, ecut, k, nb):
+    """Row-buffer (1) and lane-quad (2) x passes of the plane kernel."""
+    label(test="xmode", xmode=xmode, precision=precision, name=name, grid=grid)
+    hkl, c, V = case(grid, cell, ecut, k, nb)
+    p = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_xmode=xmode)
+    assert p.layout()["plane_xmode"] == xmode
+    got = run(p, c, V)
+    if precision == "f64":
+        ref = oracle.apply(grid, cell, ecut, k, c, V)
+        tol = TOL64
+    else:
+        ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                           V.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    err = relerr_per_band(got, ref)
+    print(name, precision, "xmode", xmode, "err", err.max())
+    assert err.max() <= tol

@@ -164,5 +164,10 @@ def test_layout_defaults():
     assert (lay["L1x"], lay["L2x"]) == (8, 12)
     assert lay["plane_lds_bytes"] <= 160 * 1024
     assert lay["sticks_per_group"] * max(lay["L1z"], lay["L2z"]) <= 256
+    assert lay["plane_xmode"] == 1
     pf = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, precision="f32")
     assert pf.layout()["plane_lds_bytes"] < lay["plane_lds_bytes"]
+    pq = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=2)
+    assert pq.layout()["plane_xmode"] == 2 and pq.layout()["plane_lds_bytes"] == 49 * 97 * 16
+    with pytest.raises(vloc.VlocError):
+        vloc.Plan((16, 18, 20), SKEW, 12.0, plane_xmode=2)

@@ -1,7 +1,8 @@
 """Build libvloc.so in-tree with hipcc for gfx950.
 
 All device code is compiled with packed FP32 instructions disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``) and with
+``-fno-signed-zeros`` so that additions of known zeros fold away.
 """
 import os
 import subprocess
@@ -18,6 +19,7 @@ ARCH = os.environ.get("VLOC_OFFLOAD_ARCH", "gfx950")
 def build(verbose: bool = False) -> str:
     out = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-fno-signed-zeros",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-o", out]
     # the .cpp files call the HIP runtime, so every source is compiled as HIP

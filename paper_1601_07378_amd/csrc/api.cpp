@@ -157,6 +157,9 @@ vloc_status upload(vloc_plan p)
         g.rl = h.plane_rl;
         g.xw = h.plane_xw;
         g.xq = h.plane_xq;
+        g.zx = h.zx;
+        g.zy = h.zy;
+        g.zz = h.zz;
         g.nst = (int)nst;
         g.npw = (int)h.npw();
         g.ngroups = h.ngroups;

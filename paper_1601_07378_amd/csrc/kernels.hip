@@ -73,6 +73,26 @@ __device__ __forceinline__ void with_codelet(int r, F &&f)
     }
 }
 
+// Compile-time size CT if non-zero, else the runtime r through the switch.
+template <int CT, typename F>
+__device__ __forceinline__ void with_size(int r, F &&f)
+{
+    if constexpr (CT > 0)
+        f(std::integral_constant<int, CT>{});
+    else
+        with_codelet(r, f);
+}
+
+// Bit n1 of a zero mask ZM is set when every input x[n2 + L2 n1] of stage A
+// is zero for every task (positions that no sphere point reaches); stage A
+// then skips those loads, the codelet folds the zeros, and the reverse stage
+// A' skips computing and storing those outputs, which nothing reads.
+template <int ZM>
+__device__ __forceinline__ constexpr bool masked(int n1)
+{
+    return ZM != 0 && ((ZM >> n1) & 1);
+}
+
 // x[k1] *= W_L^{S n2 k1}; the table holds exp(-2 pi i j / L) and n2 k1 < L.
 template <int R, int S, typename T>
 __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
@@ -92,7 +112,7 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 // (only the stick's own run is non-zero), stage B writes the z-transformed
 // stick to S[band][z][slot]; lanes of consecutive sticks write consecutive
 // slots.
-template <typename T>
+template <typename T, int CZ1, int CZ2, int ZZ>
 __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
                                                    const cx<T> *__restrict__ c,
                                                    cx<T> *__restrict__ S, long long band0)
@@ -103,9 +123,10 @@ __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
     const int s0 = gi.x, ns = gi.y, bl = blockIdx.y;
     const cx<T> *cb = c + (band0 + bl) * (long long)g.npw;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
-    const int L1 = g.L1z, L2 = g.L2z, N3 = g.N3, ldz = g.ldz;
+    const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
+    const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
 
-    with_codelet(L1, [&](auto RC) {
+    with_size<CZ1>(L1, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L2; task += blockDim.x) {
             const int j = task / L2, n2 = task - j * L2;
@@ -113,10 +134,12 @@ __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
             T xr[R], xi[R];
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
-                int i = n2 + L2 * n1 - si.z;
-                if (i < 0) i += N3;
                 cx<T> v = mk<T>(T(0), T(0));
-                if (i < si.y) v = cb[si.x + i];
+                if (!masked<ZZ>(n1)) {
+                    int i = n2 + L2 * n1 - si.z;
+                    if (i < 0) i += N3;
+                    if (i < si.y) v = cb[si.x + i];
+                }
                 xr[n1] = v.x;
                 xi[n1] = v.y;
             }
@@ -128,7 +151,7 @@ __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
         }
     });
     __syncthreads();
-    with_codelet(L2, [&](auto RC) {
+    with_size<CZ2>(L2, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L1; task += blockDim.x) {
             const int k1 = task / ns, j = task - k1 * ns;
@@ -152,7 +175,7 @@ __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
 // ------------------------------------------------------------------ K3
 // Mirror of K1: stage B' reads S[band][z][slot] (coalesced over sticks), stage
 // A' keeps only the stick's own run, scales by 1/N and writes out.
-template <typename T>
+template <typename T, int CZ1, int CZ2, int ZZ>
 __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
                                                    const cx<T> *__restrict__ S,
                                                    cx<T> *__restrict__ out, long long band0)
@@ -163,10 +186,11 @@ __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
     const int s0 = gi.x, ns = gi.y, bl = blockIdx.y;
     cx<T> *ob = out + (band0 + bl) * (long long)g.npw;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
-    const int L1 = g.L1z, L2 = g.L2z, N3 = g.N3, ldz = g.ldz;
+    const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
+    const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
     const T inv_n = T(g.inv_n);
 
-    with_codelet(L2, [&](auto RC) {
+    with_size<CZ2>(L2, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L1; task += blockDim.x) {
             const int k1 = task / ns, j = task - k1 * ns;
@@ -185,7 +209,7 @@ __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
         }
     });
     __syncthreads();
-    with_codelet(L1, [&](auto RC) {
+    with_size<CZ1>(L1, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L2; task += blockDim.x) {
             const int j = task / L2, n2 = task - j * L2;
@@ -202,6 +226,7 @@ __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
             const int4 si = t.slot_info[s0 + j];
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
+                if (masked<ZZ>(n1)) continue;
                 int i = n2 + L2 * n1 - si.z;
                 if (i < 0) i += N3;
                 if (i < si.y) ob[si.x + i] = mk<T>(xr[n1] * inv_n, xi[n1] * inv_n);
@@ -230,15 +255,6 @@ __global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
 // accesses hit distinct LDS banks; y stages map consecutive lanes to
 // consecutive columns (stride ldy, odd) for the same reason.
 
-// Compile-time size CT if non-zero, else the runtime r through the switch.
-template <int CT, typename F>
-__device__ __forceinline__ void with_size(int r, F &&f)
-{
-    if constexpr (CT > 0)
-        f(std::integral_constant<int, CT>{});
-    else
-        with_codelet(r, f);
-}
 
 // Orders LDS accesses of one wavefront (LDS executes a wave's operations in
 // issue order; this keeps the compiler from moving accesses across).
@@ -395,7 +411,7 @@ __device__ __forceinline__ void quad_twiddle(T *xr, T *xi, int q, int L,
     }
 }
 
-template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int XQ>
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY, int XQ>
 __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t,
                                            cx<T> *__restrict__ S, const T *__restrict__ V,
                                            cx<T> *__restrict__ psi, long long band0, int nb)
@@ -406,8 +422,12 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
     const int L1x = CX1 ? CX1 : g.L1x, L2x = CX2 ? CX2 : g.L2x;
     const int L1y = CY1 ? CY1 : g.L1y, L2y = CY2 ? CY2 : g.L2y;
-    const int N1 = g.N1, N2 = g.N2, nxo = g.nxo, ldy = g.ldy;
-    const int RB = g.rb, RL = g.rl;
+    // specialised splits make the line lengths and LDS strides compile-time
+    const int N1 = CX1 ? CX1 * CX2 : (XQ ? 4 * XQ : g.N1);
+    const int N2 = CY1 ? CY1 * CY2 : g.N2;
+    const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
+    const int nxo = g.nxo;
+    const int RB = g.rb, RL = CX1 ? CX1 * (CX2 + 1) : g.rl;
     cx<T> *rows = plane + nxo * ldy + wave * RB * RL;
 
     // XCD-aware order: consecutive workgroups go to different XCDs, so give
@@ -437,10 +457,12 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                 T xr[R], xi[R];
 #pragma unroll
                 for (int n1 = 0; n1 < R; ++n1) {
-                    int rel = n2 + L2y * n1 - ci.x;
-                    if (rel < 0) rel += N2;
                     cx<T> v = mk<T>(T(0), T(0));
-                    if (rel < ci.y) v = col[L2y * n1];
+                    if (!masked<ZY>(n1)) {
+                        int rel = n2 + L2y * n1 - ci.x;
+                        if (rel < 0) rel += N2;
+                        if (rel < ci.y) v = col[L2y * n1];
+                    }
                     xr[n1] = v.x;
                     xi[n1] = v.y;
                 }
@@ -541,10 +563,12 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                         T xr[R], xi[R];
 #pragma unroll
                         for (int n1 = 0; n1 < R; ++n1) {
-                            int hc = n2 + L2x * n1 - g.hmin_mod;
-                            if (hc < 0) hc += N1;
                             cx<T> v = mk<T>(T(0), T(0));
-                            if (hc < nxo) v = plane[hc * ldy + yp];
+                            if (!masked<ZX>(n1)) {
+                                int hc = n2 + L2x * n1 - g.hmin_mod;
+                                if (hc < 0) hc += N1;
+                                if (hc < nxo) v = plane[hc * ldy + yp];
+                            }
                             xr[n1] = v.x;
                             xi[n1] = v.y;
                         }
@@ -625,6 +649,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                         Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
                         for (int n1 = 0; n1 < R; ++n1) {
+                            if (masked<ZX>(n1)) continue;
                             int hc = n2 + L2x * n1 - g.hmin_mod;
                             if (hc < 0) hc += N1;
                             if (hc < nxo) plane[hc * ldy + yp] = mk<T>(xr[n1], xi[n1]);
@@ -675,6 +700,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
+                if (masked<ZY>(n1)) continue;
                 int rel = n2 + L2y * n1 - ci.x;
                 if (rel < 0) rel += N2;
                 if (rel < ci.y) col[L2y * n1] = mk<T>(xr[n1], xi[n1]);
@@ -686,12 +712,12 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
 }
 
 // LDS row-buffer variant (any split), up to 512 threads.
-template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2>
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY>
 __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *__restrict__ S,
                                                const T *__restrict__ V,
                                                cx<T> *__restrict__ psi, long long band0, int nb)
 {
-    plane_body<T, MODE, CX1, CX2, CY1, CY2, 0>(g, t, S, V, psi, band0, nb);
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0>(g, t, S, V, psi, band0, nb);
 }
 
 // Quad variant: no row buffer, so the occupied plane is the only LDS and two
@@ -701,7 +727,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per
 void k_plane_quad(Geometry g, DevTables t, cx<T> *__restrict__ S, const T *__restrict__ V,
                   cx<T> *__restrict__ psi, long long band0, int nb)
 {
-    plane_body<T, MODE, 0, 0, CY1, CY2, XQ>(g, t, S, V, psi, band0, nb);
+    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ>(g, t, S, V, psi, band0, nb);
 }
 
 // ------------------------------------------------------------ launchers
@@ -714,18 +740,31 @@ static hipError_t allow_lds(K kernel, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Line splits and zero masks compiled as specialisations of the stick
+// kernels; any other plan runs the same kernels with runtime sizes.
+#define VLOC_STICK_SPECS(X)                                                                       \
+    X(8, 12, 0x38) X(8, 12, 0) X(4, 6, 0x4) X(4, 6, 0) X(8, 16, 0x38) X(8, 16, 0)               \
+    X(8, 10, 0x38) X(8, 10, 0)
+
 template <typename T>
 hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const void *c, int64_t band0,
                             int nb, void *S, int threads, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
     size_t lds = (size_t)g.group_cap * g.ldz * sizeof(cx<T>);
-    hipError_t e = allow_lds(k_stick_fwd<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stick_fwd<T>, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
-                       reinterpret_cast<const cx<T> *>(c), reinterpret_cast<cx<T> *>(S),
-                       (long long)band0);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
+                           reinterpret_cast<const cx<T> *>(c), reinterpret_cast<cx<T> *>(S),
+                           (long long)band0);
+        return hipGetLastError();
+    };
+#define VLOC_K1(A, B, Z)                                                                           \
+    if (g.L1z == A && g.L2z == B && g.zz == Z) return go(k_stick_fwd<T, A, B, Z>);
+    VLOC_STICK_SPECS(VLOC_K1)
+#undef VLOC_K1
+    return go(k_stick_fwd<T, 0, 0, 0>);
 }
 
 template <typename T>
@@ -734,20 +773,27 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S
 {
     if (nb <= 0) return hipSuccess;
     size_t lds = (size_t)g.group_cap * g.ldz * sizeof(cx<T>);
-    hipError_t e = allow_lds(k_stick_bwd<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stick_bwd<T>, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
-                       reinterpret_cast<const cx<T> *>(S), reinterpret_cast<cx<T> *>(out),
-                       (long long)band0);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
+                           reinterpret_cast<const cx<T> *>(S), reinterpret_cast<cx<T> *>(out),
+                           (long long)band0);
+        return hipGetLastError();
+    };
+#define VLOC_K3(A, B, Z)                                                                           \
+    if (g.L1z == A && g.L2z == B && g.zz == Z) return go(k_stick_bwd<T, A, B, Z>);
+    VLOC_STICK_SPECS(VLOC_K3)
+#undef VLOC_K3
+    return go(k_stick_bwd<T, 0, 0, 0>);
 }
 
-template <typename T, int MODE, int X1, int X2, int Y1, int Y2>
+template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int ZY>
 static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, void *S, const void *V,
                                      void *psi, int64_t band0, int nb, int threads, int lds,
                                      hipStream_t st)
 {
-    auto kern = k_plane<T, MODE, X1, X2, Y1, Y2>;
+    auto kern = k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>;
     hipError_t e = allow_lds(kern, (size_t)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds, st, g, t,
@@ -789,17 +835,21 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void 
 #undef VLOC_QUAD_CASE
         return hipErrorInvalidValue;
     }
-#define VLOC_PLANE_CASE(X1, X2, Y1, Y2)                                                            \
-    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2)                                 \
-        return launch_plane_sized<T, MODE, X1, X2, Y1, Y2>(g, t, S, V, psi, band0, nb, threads,   \
-                                                           lds, st);
-    VLOC_PLANE_CASE(8, 12, 8, 12)
-    VLOC_PLANE_CASE(4, 6, 4, 6)
-    VLOC_PLANE_CASE(8, 16, 8, 16)
-    VLOC_PLANE_CASE(8, 10, 8, 10)
-    VLOC_PLANE_CASE(8, 9, 8, 12)
+#define VLOC_PLANE_CASE(X1, X2, Y1, Y2, ZX, ZY)                                                    \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && g.zx == ZX && g.zy == ZY)     \
+        return launch_plane_sized<T, MODE, X1, X2, Y1, Y2, ZX, ZY>(g, t, S, V, psi, band0, nb,    \
+                                                                   threads, lds, st);
+    VLOC_PLANE_CASE(8, 12, 8, 12, 0x38, 0x38)
+    VLOC_PLANE_CASE(8, 12, 8, 12, 0, 0)
+    VLOC_PLANE_CASE(4, 6, 4, 6, 0x4, 0x4)
+    VLOC_PLANE_CASE(4, 6, 4, 6, 0, 0)
+    VLOC_PLANE_CASE(8, 16, 8, 16, 0x38, 0x38)
+    VLOC_PLANE_CASE(8, 16, 8, 16, 0, 0)
+    VLOC_PLANE_CASE(8, 10, 8, 10, 0x38, 0x38)
+    VLOC_PLANE_CASE(8, 10, 8, 10, 0, 0)
+    VLOC_PLANE_CASE(8, 9, 8, 12, 0, 0)
 #undef VLOC_PLANE_CASE
-    return launch_plane_sized<T, MODE, 0, 0, 0, 0>(g, t, S, V, psi, band0, nb, threads, lds, st);
+    return launch_plane_sized<T, MODE, 0, 0, 0, 0, 0, 0>(g, t, S, V, psi, band0, nb, threads, lds, st);
 }
 
 template <typename T>

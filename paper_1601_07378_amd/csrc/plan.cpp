@@ -74,6 +74,23 @@ std::vector<double> twiddle_table(int L)
     return t;
 }
 
+// Bit n1 is set when no occupied position v in [lo, hi] (taken mod L) falls in
+// the stage-A input group {n2 + L2 n1 : n2 < L2}.
+static int32_t zero_mask(const Split &s, long lo, long hi)
+{
+    int32_t m = 0;
+    for (int n1 = 0; n1 < s.L1; ++n1) {
+        bool any = false;
+        for (int n2 = 0; n2 < s.L2 && !any; ++n2) {
+            long pos = n2 + (long)s.L2 * n1;
+            long r = ((pos - lo) % s.L + s.L) % s.L;
+            any = lo + r <= hi;
+        }
+        if (!any) m |= 1 << n1;
+    }
+    return m;
+}
+
 static bool reciprocal_rows(const double A[9], double B[9])
 {
     double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
@@ -218,6 +235,9 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         return VLOC_E_SPHERE;
     }
     p.nxo = p.hmax - p.hmin + 1;
+    p.zx = zero_mask(p.sx, p.hmin, p.hmax);
+    p.zy = zero_mask(p.sy, p.kmin, p.kmax);
+    p.zz = zero_mask(p.sz, lmin, lmax);
 
     // ---- launch geometry
     const int es = p.elem_bytes();

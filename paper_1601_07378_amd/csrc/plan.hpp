@@ -28,6 +28,7 @@ struct HostPlan {
     std::vector<int32_t> hkl;      // npw * 3, canonical order
     std::vector<Stick> sticks;     // canonical (h, k) order
     int32_t hmin = 0, hmax = 0, kmin = 0, kmax = 0, nxo = 0;
+    int32_t zx = 0, zy = 0, zz = 0; // stage-A input groups that are zero on every line
 
     // deal of sticks to groups; slots are numbered so that each group's
     // sticks are contiguous

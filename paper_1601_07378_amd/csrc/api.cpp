@@ -9,6 +9,7 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -160,6 +161,13 @@ vloc_status upload(vloc_plan p)
         g.zx = h.zx;
         g.zy = h.zy;
         g.zz = h.zz;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+                hipSuccess ||
+            cus < 1)
+            cus = 256;
+        const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, h.plane_lds)));
+        g.resident_plane_wgs = cus * per_cu;
         g.nst = (int)nst;
         g.npw = (int)h.npw();
         g.ngroups = h.ngroups;

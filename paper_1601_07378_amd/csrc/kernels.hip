@@ -430,23 +430,58 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     const int RB = g.rb, RL = CX1 ? CX1 * (CX2 + 1) : g.rl;
     cx<T> *rows = plane + nxo * ldy + wave * RB * RL;
 
-    // XCD-aware order: consecutive workgroups go to different XCDs, so give
-    // each XCD a contiguous run of (z, band) pairs; the bands of one z then
-    // share that XCD's L2 copy of the V plane.
-    const int nblk = gridDim.x;
-    int jb = blockIdx.x;
-    if ((nblk & 7) == 0) jb = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
-    const int z = jb / nb, bl = jb - z * nb;
-
     const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
     const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
-    cx<T> *Sz = S + ((long long)bl * g.N3 + z) * g.nst;
+    const int nst = g.nst;
+
+    // Persistent schedule over the nb * N3 planes of the launch.  Workgroup i
+    // runs on XCD i mod 8, so each XCD takes a contiguous eighth of the planes
+    // in z-major order: the bands of one z share that XCD's L2 copy of the V
+    // plane.  Every workgroup reaches the end of its range.
+    const int total = nb * g.N3;
+    int j0 = blockIdx.x, jstep = gridDim.x, jend = total;
+    if ((gridDim.x & 7) == 0 && (total & 7) == 0) {
+        const int share = total >> 3, xcd = blockIdx.x & 7;
+        j0 = xcd * share + (blockIdx.x >> 3);
+        jstep = gridDim.x >> 3;
+        jend = (xcd + 1) * share;
+    }
+    // The first PF slots of this thread keep their plane positions in
+    // registers for the whole kernel, and their values for the next plane are
+    // loaded while the current plane is transformed.
+    constexpr int PF = 4;
+    int spos[PF];
+    cx<T> sval[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        const int sl = tid + i * nthr;
+        spos[i] = sl < nst ? t.slot_info[sl].w : 0;
+        sval[i] = mk<T>(T(0), T(0));
+    }
+    auto prefetch = [&](int j) {
+        const int zz = j / nb, bb = j - zz * nb;
+        const cx<T> *Sj = S + ((long long)bb * g.N3 + zz) * nst;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            if (sl < nst) sval[i] = Sj[sl];
+        }
+    };
+    if (MODE != MODE_R2G && j0 < jend) prefetch(j0);
+
+    for (int j = j0; j < jend; j += jstep) {
+    const int z = j / nb, bl = j - z * nb;
+    cx<T> *Sz = S + ((long long)bl * g.N3 + z) * nst;
     cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
     const T *Vz = V ? V + (long long)z * N2 * N1 : nullptr;
 
     if (MODE != MODE_R2G) {
-        for (int s = tid; s < g.nst; s += nthr) plane[t.slot_info[s].w] = Sz[s];
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+            if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
+        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[t.slot_info[sl].w] = Sz[sl];
         __syncthreads();
+        if (j + jstep < jend) prefetch(j + jstep);
         // y forward, stage A (lanes along columns)
         with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
@@ -660,8 +695,8 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             }
         }
     }
-    if (MODE == MODE_G2R) return;
     __syncthreads();
+    if (MODE == MODE_G2R) continue;
 
     // y reverse, stage B' (lanes along columns)
     with_size<CY2>(L2y, [&](auto RC) {
@@ -708,7 +743,12 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         }
     });
     __syncthreads();
-    for (int s = tid; s < g.nst; s += nthr) Sz[s] = plane[t.slot_info[s].w];
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+        if (tid + i * nthr < nst) Sz[tid + i * nthr] = plane[spos[i]];
+    for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = plane[t.slot_info[sl].w];
+    __syncthreads(); // the next plane's scatter overwrites P
+    }
 }
 
 // LDS row-buffer variant (any split), up to 512 threads.
@@ -731,6 +771,17 @@ void k_plane_quad(Geometry g, DevTables t, cx<T> *__restrict__ S, const T *__res
 }
 
 // ------------------------------------------------------------ launchers
+
+// Persistent plane grid: the workgroups that are resident at once (a
+// multiple of 8 so that the XCD schedule applies), never more than the planes.
+static unsigned plane_blocks(const Geometry &g, int nb)
+{
+    long long total = (long long)nb * g.N3;
+    long long res = (long long)g.resident_plane_wgs;
+    if (res >= 8) res &= ~7LL;
+    if (res < 1) res = 1;
+    return (unsigned)(total < res ? total : res);
+}
 
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes)
@@ -796,7 +847,7 @@ static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, void
     auto kern = k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>;
     hipError_t e = allow_lds(kern, (size_t)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds, st, g, t,
+    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, nb)), dim3(threads), (size_t)lds, st, g, t,
                        reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
                        reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
     return hipGetLastError();
@@ -810,7 +861,7 @@ static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, void 
     auto kern = k_plane_quad<T, MODE, XQ, Y1, Y2>;
     hipError_t e = allow_lds(kern, (size_t)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb * g.N3), dim3(threads), (size_t)lds, st, g, t,
+    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, nb)), dim3(threads), (size_t)lds, st, g, t,
                        reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
                        reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
     return hipGetLastError();

@@ -27,6 +27,7 @@ struct Geometry {
     int xw;         // wavefronts taking part in the x pass
     int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
+    int resident_plane_wgs; // plane workgroups resident at once on the device
     int nst, npw, ngroups;
     int group_cap;  // most sticks in one group
     double inv_n;   // 1 / (N1 N2 N3)

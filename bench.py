@@ -41,7 +41,7 @@ def kernel_source_hash() -> str:
 def read_traffic(precision: str, nbands: int):
     """HBM bytes per plane-kernel launch from the committed counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"k2_plane_c2_{precision}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"vloc_apply_96cubed_256bands_{precision}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -49,7 +49,7 @@ def read_traffic(precision: str, nbands: int):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("# kernel_source_sha256_16", kv.get("kernel_source_sha256_16")) != kernel_source_hash():
         return None
     try:
         return float(kv["hbm_bytes_per_band"]) * nbands

@@ -49,7 +49,7 @@ def read_traffic(precision: str, nbands: int):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("# kernel_source_sha256_16", kv.get("kernel_source_sha256_16")) != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
         return float(kv["hbm_bytes_per_band"]) * nbands

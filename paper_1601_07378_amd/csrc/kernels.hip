@@ -113,7 +113,7 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 // stick to S[band][z][slot]; lanes of consecutive sticks write consecutive
 // slots.
 template <typename T, int CZ1, int CZ2, int ZZ>
-__global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
+__global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t,
                                                    const cx<T> *__restrict__ c,
                                                    cx<T> *__restrict__ S, long long band0)
 {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_stick_fwd(Geometry g, DevTables t,
 // Mirror of K1: stage B' reads S[band][z][slot] (coalesced over sticks), stage
 // A' keeps only the stick's own run, scales by 1/N and writes out.
 template <typename T, int CZ1, int CZ2, int ZZ>
-__global__ __launch_bounds__(256) void k_stick_bwd(Geometry g, DevTables t,
+__global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t,
                                                    const cx<T> *__restrict__ S,
                                                    cx<T> *__restrict__ out, long long band0)
 {
@@ -427,7 +427,10 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     const int N2 = CY1 ? CY1 * CY2 : g.N2;
     const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
     const int nxo = g.nxo;
-    const int RB = g.rb, RL = CX1 ? CX1 * (CX2 + 1) : g.rl;
+    // row buffer length: L1x (L2x + 1) padded to L2x mod 16 (bank spread of
+    // the stage-A writes across two rows); the host uses the same rule
+    const int RB = g.rb;
+    const int RL = CX1 ? CX1 * (CX2 + 1) + (((CX2 - CX1 * (CX2 + 1)) % 16 + 16) % 16) : g.rl;
     cx<T> *rows = plane + nxo * ldy + wave * RB * RL;
 
     const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);

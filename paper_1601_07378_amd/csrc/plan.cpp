@@ -242,12 +242,17 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     // ---- launch geometry
     const int es = p.elem_bytes();
     const int Lz = grid[2];
-    p.stick_threads = 256;
+    // stick kernels: FP64 groups of ~21 sticks on 256 threads, FP32 groups of
+    // ~32 sticks on 384 threads (measured best at 96^3)
     int tasks_per_stick = std::max(p.sz.L1, p.sz.L2);
+    const int want_threads = es == 16 ? 256 : 384;
     p.group_cap = p.opt.sticks_per_group ? p.opt.sticks_per_group
-                                         : std::max(1, p.stick_threads / tasks_per_stick);
+                                         : std::max(1, want_threads / tasks_per_stick);
     p.group_cap = std::min<int32_t>(p.group_cap, (int32_t)p.sticks.size());
     p.ldz = Lz + 1;
+    p.stick_threads = (int)std::min<int64_t>(
+        512, std::max<int64_t>(64, ((int64_t)std::min<int64_t>(p.group_cap, p.nst()) *
+                                        tasks_per_stick + 63) / 64 * 64));
     const int64_t nst = p.nst();
     p.ngroups = (int32_t)((nst + p.group_cap - 1) / p.group_cap);
 
@@ -287,6 +292,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     const int64_t plane_bytes = (int64_t)p.nxo * p.ldy * es;
     const int64_t lds_max = 160 * 1024;
     p.plane_rl = p.sx.L1 * (p.sx.L2 + 1);
+    p.plane_rl += ((p.sx.L2 - p.plane_rl) % 16 + 16) % 16; // same rule as the kernel
     const int nwaves = (p.opt.plane_threads ? p.opt.plane_threads : 512) / 64;
     p.plane_threads = nwaves * 64;
     // Choose (x waves, rows per batch) by an estimate of the plane time in

@@ -146,6 +146,36 @@ vloc_status vloc_plan_enable_timing(vloc_plan plan, int32_t enable);
  * and resets the record. */
 vloc_status vloc_plan_read_timing(vloc_plan plan, double ms[3], int64_t launches[3]);
 
+/* ------------------------------------------------ energy and its gradients */
+/* For the local-potential energy of weighted bands,
+ *   E = sum_n w_n Re <c_n | V c_n>,  with out_n = V_loc c_n from vloc_apply,
+ * the gradient with respect to V(j) is the weighted density
+ *   dE/dV(j) = (1/N) sum_n w_n |psi_n(j)|^2   (psi_n as defined above),
+ * and, V_loc being Hermitian, dE/d(Re c) + i dE/d(Im c) = 2 w_n (V c_n)(g)
+ * (Sec. 2: the operator's action; its Hermiticity follows from V real).
+ * Reductions accumulate in FP64 in a fixed order for either plan precision;
+ * no atomics, so results are bitwise reproducible.  All pointers are device
+ * pointers; the calls are stream-ordered like vloc_apply. */
+
+/* e[n] = Re sum_g conj(a_n(g)) b_n(g), n < nbands.  a, b: [nbands][npw]
+ * complex of the plan precision; e: double[nbands]. */
+vloc_status vloc_band_dot(vloc_plan plan, const void *a, const void *b, int64_t nbands, double *e);
+/* E[0] = sum_n w[n] x[n] over n < nbands (doubles). */
+vloc_status vloc_weighted_sum(vloc_plan plan, const double *x, const double *w, int64_t nbands,
+                              double *E);
+/* rho(j) += s (1/N) sum_n w_n |psi_n(j)|^2 for n < nbands.  psi_n is recomputed
+ * from c_n band chunk by band chunk inside the plane kernel and never stored;
+ * partial sums are FP64.  rho: double [N3][N2][N1] (accumulated into);
+ * w: double[nbands]; scale: one double s, or NULL for 1.  Needs the row-buffer
+ * x pass (plane_xmode 0 or 1); VLOC_E_INVALID otherwise. */
+vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const double *w,
+                         const double *scale, double *rho);
+/* y_n = factor * s * w_n * x_n for n < nbands; w (double[nbands]) and scale
+ * (one double s) may be NULL for 1; x, y: [nbands][npw] complex of the plan
+ * precision; y may equal x. */
+vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, const double *w,
+                             const double *scale, double factor, void *y);
+
 /* ------------------------------------------- diagnostic full-grid transforms */
 /* Same conventions as vloc_apply: psi_r[n] = psi_n on the whole grid. */
 vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r);

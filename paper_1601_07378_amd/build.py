@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvloc.so")
-SOURCES = ["kernels.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "reduce.hip", "plan.cpp", "api.cpp"]
 ARCH = os.environ.get("VLOC_OFFLOAD_ARCH", "gfx950")
 
 

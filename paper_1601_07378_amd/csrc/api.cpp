@@ -32,6 +32,8 @@ struct vloc_plan_s {
     double2 *d_twx64 = nullptr;
     void *d_S = nullptr;
     size_t S_bytes = 0;
+    double *d_partial = nullptr; // density partial planes
+    size_t partial_bytes = 0;
     Geometry geo{};
     // kernel timing: events[4*i .. 4*i+3] bracket K1, K2, K3 of chunk launch i
     bool timing = false;
@@ -67,6 +69,9 @@ void free_device(vloc_plan p)
     for (void *&t : p->d_tw)
         if (t) (void)hipFree(t), t = nullptr;
     if (p->d_S) (void)hipFree(p->d_S);
+    if (p->d_partial) (void)hipFree(p->d_partial);
+    p->d_partial = nullptr;
+    p->partial_bytes = 0;
     p->d_slot = nullptr;
     p->d_groups = nullptr;
     p->d_S = nullptr;
@@ -168,6 +173,7 @@ vloc_status upload(vloc_plan p)
             cus = 256;
         const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, h.plane_lds)));
         g.resident_plane_wgs = cus * per_cu;
+        g.nsub = 1;
         g.nst = (int)nst;
         g.npw = (int)h.npw();
         g.ngroups = h.ngroups;
@@ -227,6 +233,8 @@ DevTables tables(vloc_plan p)
     t.twy = p->d_tw[1];
     t.twz = p->d_tw[2];
     t.twx64 = p->d_twx64;
+    t.partial = p->d_partial;
+    t.wts = nullptr;
     return t;
 }
 
@@ -246,7 +254,7 @@ hipError_t next_events(vloc_plan p, hipEvent_t *ev)
 
 template <typename T>
 vloc_status run_chunks(vloc_plan p, int mode, const void *in, int64_t nbands, const void *V,
-                       void *out)
+                       void *out, const double *wts = nullptr)
 {
     const HostPlan &h = p->hp;
     const int64_t chunk = nbands < h.band_chunk ? nbands : h.band_chunk;
@@ -254,6 +262,7 @@ vloc_status run_chunks(vloc_plan p, int mode, const void *in, int64_t nbands, co
     if (s != VLOC_OK) return s;
     const Geometry &g = p->geo;
     DevTables t = tables(p);
+    t.wts = wts;
     hipError_t e;
     for (int64_t b0 = 0; b0 < nbands; b0 += chunk) {
         int nb = (int)((nbands - b0) < chunk ? (nbands - b0) : chunk);
@@ -273,7 +282,7 @@ vloc_status run_chunks(vloc_plan p, int mode, const void *in, int64_t nbands, co
                             p->stream);
         if (e != hipSuccess) return hip_fail(e, "plane launch");
         if (p->timing) (void)hipEventRecord(ev[2], p->stream);
-        if (mode != MODE_G2R) {
+        if (mode != MODE_G2R && mode != MODE_DENSITY) {
             e = launch_stick_bwd<T>(g, t, p->d_S, out, b0, nb, h.stick_threads, p->stream);
             if (e != hipSuccess) return hip_fail(e, "stick backward launch");
         }
@@ -407,7 +416,8 @@ vloc_status vloc_plan_read_timing(vloc_plan plan, double ms[3], int64_t launches
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
         int mode = plan->rec_modes[i];
         for (int k = 0; k < 3; ++k) {
-            if ((k == 0 && mode == MODE_R2G) || (k == 2 && mode == MODE_G2R)) continue;
+            if ((k == 0 && mode == MODE_R2G) || (k == 2 && (mode == MODE_G2R || mode == MODE_DENSITY)))
+                continue;
             float t = 0.f;
             e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
             if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
@@ -420,6 +430,109 @@ vloc_status vloc_plan_read_timing(vloc_plan plan, double ms[3], int64_t launches
     if (ms) std::memcpy(ms, acc, sizeof acc);
     if (launches) std::memcpy(launches, cnt, sizeof cnt);
     return VLOC_OK;
+}
+
+vloc_status vloc_band_dot(vloc_plan plan, const void *a, const void *b, int64_t nbands, double *e)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!a || !b || !e) return fail(VLOC_E_INVALID, "NULL a, b or e");
+    vloc_status s = upload(plan);
+    if (s != VLOC_OK) return s;
+    hipError_t err = plan->hp.opt.precision == VLOC_F32
+                         ? launch_band_dot<float>(a, b, plan->hp.npw(), nbands, e, plan->stream)
+                         : launch_band_dot<double>(a, b, plan->hp.npw(), nbands, e, plan->stream);
+    return err == hipSuccess ? VLOC_OK : hip_fail(err, "band dot launch");
+}
+
+vloc_status vloc_weighted_sum(vloc_plan plan, const double *x, const double *w, int64_t nbands,
+                              double *E)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (!x || !w || !E) return fail(VLOC_E_INVALID, "NULL x, w or E");
+    vloc_status s = upload(plan);
+    if (s != VLOC_OK) return s;
+    hipError_t err = launch_weighted_sum(x, w, nbands, E, plan->stream);
+    return err == hipSuccess ? VLOC_OK : hip_fail(err, "weighted sum launch");
+}
+
+vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, const double *w,
+                             const double *scale, double factor, void *y)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!x || !y) return fail(VLOC_E_INVALID, "NULL x or y");
+    vloc_status s = upload(plan);
+    if (s != VLOC_OK) return s;
+    const int64_t npw = plan->hp.npw();
+    hipError_t err =
+        plan->hp.opt.precision == VLOC_F32
+            ? launch_scale_bands<float>(x, npw, nbands, w, scale, factor, y, plan->stream)
+            : launch_scale_bands<double>(x, npw, nbands, w, scale, factor, y, plan->stream);
+    return err == hipSuccess ? VLOC_OK : hip_fail(err, "band scaling launch");
+}
+
+vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const double *w,
+                         const double *scale, double *rho)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!c || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, w or rho");
+    if (plan->hp.plane_xq) return fail(VLOC_E_INVALID, "density needs the row-buffer x pass");
+    vloc_status s = upload(plan);
+    if (s != VLOC_OK) return s;
+    HostPlan &h = plan->hp;
+    Geometry &g = plan->geo;
+    const int64_t N = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
+    const int64_t chunk = nbands < h.band_chunk ? nbands : h.band_chunk;
+    // band subsets per launch: items N3 * nsub fill the resident workgroups in
+    // whole rounds where possible (fewest idle slots, then fewest subsets)
+    {
+        const int R = std::max(1, g.resident_plane_wgs);
+        const int lo = std::max(1, (R + h.grid[2] - 1) / h.grid[2]);
+        int best = lo;
+        double best_w = 2.0;
+        for (int ns = lo; ns <= 4 * lo && ns <= chunk; ++ns) {
+            const int64_t items = (int64_t)h.grid[2] * ns;
+            const double rounds = (double)((items + R - 1) / R);
+            const double waste = rounds * R / (double)items;
+            if (waste < best_w - 1e-9) {
+                best_w = waste;
+                best = ns;
+            }
+        }
+        g.nsub = (int)std::min<int64_t>(best, chunk);
+    }
+    const size_t need = (size_t)g.nsub * (size_t)N * sizeof(double);
+    if (need > plan->partial_bytes) {
+        if (plan->d_partial) {
+            hipError_t e = hipStreamSynchronize(plan->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipFree(plan->d_partial);
+            plan->d_partial = nullptr;
+            plan->partial_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&plan->d_partial, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            plan->d_partial = nullptr;
+            return fail(VLOC_E_NOMEM, "density buffer allocation failed");
+        }
+        plan->partial_bytes = need;
+    }
+    hipError_t e = launch_fill_f64(plan->d_partial, (int64_t)g.nsub * N, 0.0, plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    s = h.opt.precision == VLOC_F32 ? run_chunks<float>(plan, MODE_DENSITY, c, nbands, nullptr,
+                                                        nullptr, w)
+                                    : run_chunks<double>(plan, MODE_DENSITY, c, nbands, nullptr,
+                                                         nullptr, w);
+    if (s != VLOC_OK) return s;
+    e = launch_density_reduce(plan->d_partial, g.nsub, N, g.inv_n, scale, rho, plan->stream);
+    return e == hipSuccess ? VLOC_OK : hip_fail(e, "density reduce launch");
 }
 
 vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw)

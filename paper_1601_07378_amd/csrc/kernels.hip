@@ -437,11 +437,17 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
     const int nst = g.nst;
 
-    // Persistent schedule over the nb * N3 planes of the launch.  Workgroup i
-    // runs on XCD i mod 8, so each XCD takes a contiguous eighth of the planes
-    // in z-major order: the bands of one z share that XCD's L2 copy of the V
-    // plane.  Every workgroup reaches the end of its range.
-    const int total = nb * g.N3;
+    // Work items: a plane (z, band) for the transforms; for the density a
+    // (z, band subset) pair whose bands this workgroup runs one after another,
+    // so that it alone updates the subset's partial density plane.
+    // Persistent schedule: workgroup i runs on XCD i mod 8, so each XCD takes a
+    // contiguous eighth of the items in z-major order (the bands of one z
+    // share that XCD's L2 copy of the V plane).  Every workgroup reaches the
+    // end of its range.
+    constexpr bool DENS = (MODE == MODE_DENSITY);
+    const int nsub = DENS ? g.nsub : 1;
+    const int bps = DENS ? (nb + nsub - 1) / nsub : 1;
+    const int total = DENS ? g.N3 * nsub : nb * g.N3;
     int j0 = blockIdx.x, jstep = gridDim.x, jend = total;
     if ((gridDim.x & 7) == 0 && (total & 7) == 0) {
         const int share = total >> 3, xcd = blockIdx.x & 7;
@@ -449,6 +455,31 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         jstep = gridDim.x >> 3;
         jend = (xcd + 1) * share;
     }
+    auto plane_of = [&](int j, int k, int &zz, int &bb) {
+        if (DENS) {
+            zz = j / nsub;
+            bb = (j - zz * nsub) * bps + k;
+        } else {
+            zz = j / nb;
+            bb = j - zz * nb;
+        }
+    };
+    // next non-empty plane of this workgroup's sequence; false at the end
+    auto advance = [&](int &j, int &k) -> bool {
+        for (;;) {
+            if (DENS && k + 1 < bps)
+                ++k;
+            else {
+                j += jstep;
+                k = 0;
+            }
+            if (j >= jend) return false;
+            int zz, bb;
+            plane_of(j, k, zz, bb);
+            if (bb < nb) return true;
+            k = bps; // rest of this subset is empty: go to the next item
+        }
+    };
     // The first PF slots of this thread keep their plane positions in
     // registers for the whole kernel, and their values for the next plane are
     // loaded while the current plane is transformed.
@@ -461,8 +492,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         spos[i] = sl < nst ? t.slot_info[sl].w : 0;
         sval[i] = mk<T>(T(0), T(0));
     }
-    auto prefetch = [&](int j) {
-        const int zz = j / nb, bb = j - zz * nb;
+    auto prefetch = [&](int zz, int bb) {
         const cx<T> *Sj = S + ((long long)bb * g.N3 + zz) * nst;
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
@@ -470,13 +500,26 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             if (sl < nst) sval[i] = Sj[sl];
         }
     };
-    if (MODE != MODE_R2G && j0 < jend) prefetch(j0);
+    int jc = j0, kc = 0;
+    bool have = jc < jend;
+    if (have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        if (bb >= nb) have = advance(jc, kc);
+    }
+    if (MODE != MODE_R2G && have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        prefetch(zz, bb);
+    }
 
-    for (int j = j0; j < jend; j += jstep) {
-    const int z = j / nb, bl = j - z * nb;
+    for (; have; have = advance(jc, kc)) {
+    int z, bl;
+    plane_of(jc, kc, z, bl);
     cx<T> *Sz = S + ((long long)bl * g.N3 + z) * nst;
     cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
     const T *Vz = V ? V + (long long)z * N2 * N1 : nullptr;
+    double *accz = DENS ? t.partial + ((long long)(bl / bps) * g.N3 + z) * N2 * N1 : nullptr;
 
     if (MODE != MODE_R2G) {
 #pragma unroll
@@ -484,7 +527,13 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
         for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[t.slot_info[sl].w] = Sz[sl];
         __syncthreads();
-        if (j + jstep < jend) prefetch(j + jstep);
+        {
+            int jn = jc, kn = kc, zz, bb;
+            if (advance(jn, kn)) {
+                plane_of(jn, kn, zz, bb);
+                prefetch(zz, bb);
+            }
+        }
         // y forward, stage A (lanes along columns)
         with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
@@ -653,6 +702,16 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                         cx<T> *dst = psiz + (long long)y * N1 + k1;
 #pragma unroll
                         for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
+                    } else if (MODE == MODE_DENSITY) {
+                        // w_b |psi_b(x, y, z)|^2 into this subset's partial plane;
+                        // the lane owns these points for every band of the subset
+                        const double wb = t.wts[band0 + bl];
+                        double *acc = accz + (long long)y * N1 + k1;
+#pragma unroll
+                        for (int k2 = 0; k2 < R; ++k2) {
+                            const double a = (double)xr[k2], b = (double)xi[k2];
+                            acc[L1x * k2] += wb * (a * a + b * b);
+                        }
                     } else {
                         if (MODE == MODE_APPLY) {
 #pragma unroll
@@ -668,7 +727,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                 }
             });
             wave_sync();
-            if (MODE != MODE_G2R) {
+            if (MODE != MODE_G2R && MODE != MODE_DENSITY) {
                 with_size<CX1>(L1x, [&](auto RC) {
                     constexpr int R = decltype(RC)::value;
                     for (int task = lane; task < nr * L2x; task += 64) {
@@ -699,7 +758,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         }
     }
     __syncthreads();
-    if (MODE == MODE_G2R) continue;
+    if (MODE == MODE_G2R || MODE == MODE_DENSITY) continue;
 
     // y reverse, stage B' (lanes along columns)
     with_size<CY2>(L2y, [&](auto RC) {
@@ -877,7 +936,7 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void 
                                     void *psi, int64_t band0, int nb, int threads, int lds,
                                     hipStream_t st)
 {
-    if (g.xq) {
+    if constexpr (MODE != MODE_DENSITY) if (g.xq) {
 #define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
         if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
             return launch_plane_quad<T, MODE, XQ, Y1, Y2>(g, t, S, V, psi, band0, nb, threads,    \
@@ -919,6 +978,10 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, int mode, void *S
         return launch_plane_mode<T, MODE_G2R>(g, t, S, V, psi, band0, nb, threads, lds_bytes, st);
     case MODE_R2G:
         return launch_plane_mode<T, MODE_R2G>(g, t, S, V, psi, band0, nb, threads, lds_bytes, st);
+    case MODE_DENSITY:
+        if (g.xq) return hipErrorInvalidValue; // density runs on the row-buffer x pass only
+        return launch_plane_mode<T, MODE_DENSITY>(g, t, S, V, psi, band0, nb, threads, lds_bytes,
+                                                  st);
     default: return hipErrorInvalidValue;
     }
 }

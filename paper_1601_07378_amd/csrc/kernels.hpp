@@ -5,7 +5,7 @@
 
 namespace vloc {
 
-enum PlaneMode { MODE_APPLY = 0, MODE_G2R = 1, MODE_R2G = 2 };
+enum PlaneMode { MODE_APPLY = 0, MODE_G2R = 1, MODE_R2G = 2, MODE_DENSITY = 3 };
 
 // Tables and sizes shared by the kernels of one plan (device pointers).
 struct DevTables {
@@ -14,6 +14,8 @@ struct DevTables {
     const int2 *cols;       // per occupied x-plane: {first k mod N2, number of k}
     const void *twx, *twy, *twz; // exp(-2 pi i j / L), complex of the plan precision
     const double2 *twx64;        // exp(-2 pi i j / N1) in FP64 (quad x pass)
+    double *partial;             // density: [nsub][N3][N2][N1] partial sums (FP64)
+    const double *wts;           // density: band weights (FP64)
 };
 
 struct Geometry {
@@ -28,6 +30,7 @@ struct Geometry {
     int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
     int resident_plane_wgs; // plane workgroups resident at once on the device
+    int nsub;       // density: band subsets per launch
     int nst, npw, ngroups;
     int group_cap;  // most sticks in one group
     double inv_n;   // 1 / (N1 N2 N3)
@@ -43,6 +46,19 @@ template <typename T>
 hipError_t launch_plane(const Geometry &g, const DevTables &t, int mode, void *S, const void *V,
                         void *psi, int64_t band0, int nb, int threads, int lds_bytes,
                         hipStream_t st);
+// Density helpers (reduce.hip): FP64 reductions and band scaling.
+hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
+hipError_t launch_density_reduce(const double *partial, int nsub, int64_t n, double inv_n,
+                                 const double *scale, double *rho, hipStream_t st);
+template <typename T>
+hipError_t launch_band_dot(const void *a, const void *b, int64_t npw, int64_t nb, double *out,
+                           hipStream_t st);
+hipError_t launch_weighted_sum(const double *x, const double *w, int64_t n, double *out,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const double *w,
+                              const double *scale, double factor, void *y, hipStream_t st);
+
 // K3: stick z-transforms (r -> G direction) with 1/N, gathering into out.
 template <typename T>
 hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S, void *out,

@@ -1,0 +1,173 @@
+// reduce.hip -- FP64 reductions and band scaling around the V_loc path.
+//
+// For E = sum_n w_n Re <c_n | V c_n> (the local-potential energy of weighted
+// bands):
+//   e_n    = Re sum_g conj(c_n(g)) out_n(g)              (band_dot, FP64)
+//   E      = sum_n w_n e_n                               (weighted_sum, FP64)
+//   dE/dV  = (1/N) sum_n w_n |psi_n(j)|^2                (density_reduce of the
+//            partial planes the plane kernel accumulates in FP64)
+//   dE/dc_n = 2 w_n (V c_n)(g)                           (scale_bands)
+// All sums run in a fixed order (no atomics), so results are reproducible.
+#include "kernels.hpp"
+
+namespace vloc {
+
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<double> {
+    using type = double2;
+};
+template <>
+struct Cplx<float> {
+    using type = float2;
+};
+
+__global__ void k_fill_f64(double *x, long long n, double v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// rho[j] += scale * inv_n * sum_{s < nsub} partial[s][j], s ascending.
+__global__ void k_density_reduce(const double *__restrict__ partial, int nsub, long long n,
+                                 double inv_n, const double *__restrict__ scale,
+                                 double *__restrict__ rho)
+{
+    const double f = inv_n * (scale ? scale[0] : 1.0);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < nsub; ++s) acc += partial[(long long)s * n + i];
+        rho[i] += f * acc;
+    }
+}
+
+// Fixed-order tree sum of one value per thread over a 256-thread block.
+__device__ double block_sum_256(double v, double *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// out[n] = Re sum_g conj(a[n][g]) b[n][g]: one block per band, FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_dot(const typename Cplx<T>::type *__restrict__ a,
+                                                  const typename Cplx<T>::type *__restrict__ b,
+                                                  long long npw, double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    const long long base = (long long)blockIdx.x * npw;
+    double acc = 0.0;
+    for (long long g = threadIdx.x; g < npw; g += 256) {
+        const auto x = a[base + g];
+        const auto y = b[base + g];
+        acc += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+    }
+    const double s = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// out[0] = sum_n w[n] x[n], one block, fixed order.
+__global__ __launch_bounds__(256) void k_weighted_sum(const double *__restrict__ x,
+                                                      const double *__restrict__ w, long long n,
+                                                      double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) acc += w[i] * x[i];
+    const double s = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// y[n][g] = factor * scale * w[n] * x[n][g] (w, scale may be NULL = 1).
+template <typename T>
+__global__ void k_scale_bands(const typename Cplx<T>::type *__restrict__ x, long long npw,
+                              long long nb, const double *__restrict__ w,
+                              const double *__restrict__ scale, double factor,
+                              typename Cplx<T>::type *__restrict__ y)
+{
+    const double f0 = factor * (scale ? scale[0] : 1.0);
+    const long long tot = npw * nb;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long n = i / npw;
+        const T f = (T)(f0 * (w ? w[n] : 1.0));
+        auto v = x[i];
+        v.x *= f;
+        v.y *= f;
+        y[i] = v;
+    }
+}
+
+static unsigned grid_for(long long n, unsigned cap = 4096)
+{
+    long long b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    return (unsigned)(b < cap ? b : cap);
+}
+
+hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, st, x, (long long)n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_reduce(const double *partial, int nsub, int64_t n, double inv_n,
+                                 const double *scale, double *rho, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_density_reduce, dim3(grid_for(n)), dim3(256), 0, st, partial, nsub,
+                       (long long)n, inv_n, scale, rho);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_dot(const void *a, const void *b, int64_t npw, int64_t nb, double *out,
+                           hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL(k_band_dot<T>, dim3((unsigned)nb), dim3(256), 0, st,
+                       reinterpret_cast<const C *>(a), reinterpret_cast<const C *>(b),
+                       (long long)npw, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const double *x, const double *w, int64_t n, double *out,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(256), 0, st, x, w, (long long)n, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const double *w,
+                              const double *scale, double factor, void *y, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL(k_scale_bands<T>, dim3(grid_for(npw * nb)), dim3(256), 0, st,
+                       reinterpret_cast<const C *>(x), (long long)npw, (long long)nb, w, scale,
+                       factor, reinterpret_cast<C *>(y));
+    return hipGetLastError();
+}
+
+template hipError_t launch_band_dot<double>(const void *, const void *, int64_t, int64_t,
+                                            double *, hipStream_t);
+template hipError_t launch_band_dot<float>(const void *, const void *, int64_t, int64_t,
+                                           double *, hipStream_t);
+template hipError_t launch_scale_bands<double>(const void *, int64_t, int64_t, const double *,
+                                               const double *, double, void *, hipStream_t);
+template hipError_t launch_scale_bands<float>(const void *, int64_t, int64_t, const double *,
+                                              const double *, double, void *, hipStream_t);
+
+} // namespace vloc

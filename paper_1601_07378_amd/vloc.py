@@ -33,6 +33,7 @@ EXPORTS = [
     "vloc_apply", "vloc_plan_npw", "vloc_plan_gvectors", "vloc_plan_sticks",
     "vloc_plan_balance", "vloc_plan_stick_groups", "vloc_plan_layout", "vloc_g2r", "vloc_r2g",
     "vloc_status_string", "vloc_last_error", "vloc_plan_enable_timing", "vloc_plan_read_timing",
+    "vloc_band_dot", "vloc_weighted_sum", "vloc_density", "vloc_scale_bands",
 ]
 
 
@@ -83,6 +84,10 @@ def lib():
         "vloc_r2g": [vp, vp, i64, vp],
         "vloc_plan_enable_timing": [vp, ctypes.c_int32],
         "vloc_plan_read_timing": [vp, ctypes.POINTER(ctypes.c_double), i64p],
+        "vloc_band_dot": [vp, vp, vp, i64, vp],
+        "vloc_weighted_sum": [vp, vp, vp, i64, vp],
+        "vloc_density": [vp, vp, i64, vp, vp, vp],
+        "vloc_scale_bands": [vp, vp, i64, vp, vp, ctypes.c_double, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -219,6 +224,77 @@ class Plan:
         self.set_stream(stream)
         check(lib().vloc_apply(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
                                ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    # ---- energy and gradient pieces (FP64 reductions)
+    def _check_c(self, c, name="c"):
+        ct, _ = self._dtypes()
+        if c.dtype != ct or not c.is_cuda or not c.is_contiguous() or c.dim() != 2 \
+                or c.shape[1] != self.npw:
+            raise ValueError(f"{name} must be a contiguous device tensor (nbands, npw) of {ct}")
+
+    @staticmethod
+    def _f64(x, n, name):
+        import torch
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} values")
+
+    def band_dot(self, a, b, stream=None):
+        """Re sum_g conj(a_n) b_n per band, float64 (nbands,)."""
+        import torch
+        self._check_c(a, "a")
+        self._check_c(b, "b")
+        e = torch.empty(a.shape[0], dtype=torch.float64, device=a.device)
+        self.set_stream(stream)
+        check(lib().vloc_band_dot(self._h, ctypes.c_void_p(a.data_ptr()),
+                                  ctypes.c_void_p(b.data_ptr()), a.shape[0],
+                                  ctypes.c_void_p(e.data_ptr())))
+        return e
+
+    def weighted_sum(self, x, w, stream=None):
+        import torch
+        self._f64(x, x.numel(), "x")
+        self._f64(w, x.numel(), "w")
+        E = torch.empty((), dtype=torch.float64, device=x.device)
+        self.set_stream(stream)
+        check(lib().vloc_weighted_sum(self._h, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(w.data_ptr()), x.numel(),
+                                      ctypes.c_void_p(E.data_ptr())))
+        return E
+
+    def density(self, c, w, scale=None, rho=None, stream=None):
+        """rho += scale (1/N) sum_n w_n |psi_n|^2 (float64 [N3, N2, N1])."""
+        import torch
+        self._check_c(c)
+        self._f64(w, c.shape[0], "w")
+        N1, N2, N3 = self.grid
+        if rho is None:
+            rho = torch.zeros((N3, N2, N1), dtype=torch.float64, device=c.device)
+        self._f64(rho, N1 * N2 * N3, "rho")
+        if scale is not None:
+            self._f64(scale, 1, "scale")
+        self.set_stream(stream)
+        check(lib().vloc_density(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
+                                 ctypes.c_void_p(w.data_ptr()),
+                                 ctypes.c_void_p(scale.data_ptr() if scale is not None else 0),
+                                 ctypes.c_void_p(rho.data_ptr())))
+        return rho
+
+    def scale_bands(self, x, w=None, scale=None, factor=1.0, out=None, stream=None):
+        """out_n = factor * scale * w_n * x_n."""
+        import torch
+        self._check_c(x, "x")
+        if w is not None:
+            self._f64(w, x.shape[0], "w")
+        if scale is not None:
+            self._f64(scale, 1, "scale")
+        if out is None:
+            out = torch.empty_like(x)
+        self.set_stream(stream)
+        check(lib().vloc_scale_bands(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                     ctypes.c_void_p(w.data_ptr() if w is not None else 0),
+                                     ctypes.c_void_p(scale.data_ptr() if scale is not None else 0),
+                                     float(factor), ctypes.c_void_p(out.data_ptr())))
         return out
 
     def g2r(self, c, out=None, stream=None):

@@ -1,0 +1,185 @@
+"""GPU checks of the differentiable local-potential energy
+E = sum_n w_n Re <c_n | V c_n> and its gradients (torch.autograd.Function over
+libvloc's kernels).
+
+References: the CPU oracle (E from oracle.apply; dE/dc = 2 w_n V c_n; dE/dV =
+(1/N) sum_n w_n |psi_n|^2 from oracle.g2r; dE/dw = e_n) and central finite
+differences of the GPU energy itself.  E is quadratic in c and linear in V, so
+central differences have no truncation error; with h = 1e-4 the round-off is
+about eps |E| / h, far below the 1e-7 relative gate."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+vloc = pytest.importorskip("paper_1601_07378_amd.vloc")
+ag = pytest.importorskip("paper_1601_07378_amd.autograd")
+
+SKEW = np.array([[6.0, 0.3, -0.2], [0.5, 7.0, 0.4], [-0.3, 0.6, 6.5]])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(require_gpu):
+    yield
+
+
+def label(**kw):
+    print("CASE", kw, flush=True)
+
+
+def tensors(c, V, w, precision):
+    ct, rt = (torch.complex128, torch.float64) if precision == "f64" else \
+        (torch.complex64, torch.float32)
+    tc = torch.from_numpy(np.ascontiguousarray(c)).to("cuda", ct).requires_grad_(True)
+    tV = torch.from_numpy(np.ascontiguousarray(V)).to("cuda", rt).requires_grad_(True)
+    tw = torch.from_numpy(np.ascontiguousarray(w)).to("cuda", torch.float64).requires_grad_(True)
+    return tc, tV, tw
+
+
+def oracle_refs(grid, cell, ecut, k, c, V, w):
+    out = oracle.apply(grid, cell, ecut, k, c, V)
+    e = np.real(np.sum(np.conj(c) * out, axis=1))
+    psi = oracle.g2r(grid, cell, ecut, k, c).reshape(c.shape[0], -1)
+    N = np.prod(grid)
+    rho = (w[:, None] * np.abs(psi) ** 2).sum(0) / N
+    return float(np.dot(w, e)), 2 * w[:, None] * out, rho, e
+
+
+GRAD_CASES = [
+    ("c1", (24, 24, 24), synth.cubic_cell(), 18.0, (0, 0, 0), 8),
+    ("skew_k_generic", (16, 18, 20), SKEW, 12.0, (0.25, 1 / 3, 0.0), 5),
+    ("ortho_k", (72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0.25, 0.0), 3),
+    ("c2_96", (96, 96, 96), synth.cubic_cell(), 288.0, (0, 0, 0), 6),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,grid,cell,ecut,k,nb", GRAD_CASES)
+def test_energy_gradients_vs_oracle(precision, name, grid, cell, ecut, k, nb):
+    label(test="grad_vs_oracle", name=name, precision=precision)
+    hkl = oracle.sphere_py(cell, ecut, k)
+    c = synth.coefficients(hkl, nb, k)
+    V = synth.potential(grid, 4)
+    w = synth.band_weights(nb)
+    if precision == "f32":  # compare against the oracle on the rounded inputs
+        c = c.astype(np.complex64).astype(np.complex128)
+        V = V.astype(np.float32).astype(np.float64)
+    plan = vloc.Plan(grid, cell, ecut, k, precision=precision)
+    tc, tV, tw = tensors(c, V, w, precision)
+    E = ag.local_energy(plan, tc, tV, tw)
+    E.backward()
+    torch.cuda.synchronize()
+    E_ref, gc_ref, rho_ref, e_ref = oracle_refs(grid, cell, ecut, k, c, V, w)
+    tol = 1e-12 if precision == "f64" else 3e-6
+    print(name, precision, "E", E.item(), E_ref)
+    assert abs(E.item() - E_ref) <= tol * abs(E_ref)
+    assert relerr(tc.grad.cpu().numpy(), gc_ref) <= tol
+    assert relerr(tV.grad.cpu().numpy().ravel(), rho_ref) <= tol
+    assert relerr(tw.grad.cpu().numpy(), e_ref) <= tol
+
+
+def test_density_is_deterministic_and_chunk_invariant():
+    grid, cell, ecut = (24, 24, 24), synth.cubic_cell(), 18.0
+    label(test="density_determinism")
+    hkl = oracle.sphere_py(cell, ecut)
+    c = torch.from_numpy(synth.coefficients(hkl, 13)).cuda()
+    w = torch.from_numpy(synth.band_weights(13)).cuda()
+    r1 = vloc.Plan(grid, cell, ecut).density(c, w)
+    r2 = vloc.Plan(grid, cell, ecut).density(c, w)
+    r3 = vloc.Plan(grid, cell, ecut, band_chunk=4).density(c, w)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2)
+    # chunking changes the grouping of the FP64 sums, not the value beyond rounding
+    assert relerr(r3.cpu().numpy(), r1.cpu().numpy()) < 1e-14
+    # density accumulates into rho and scales
+    rho = torch.ones_like(r1)
+    s = torch.tensor([2.5], dtype=torch.float64, device="cuda")
+    vloc.Plan(grid, cell, ecut).density(c, w, scale=s, rho=rho)
+    assert relerr((rho - 1).cpu().numpy(), 2.5 * r1.cpu().numpy()) < 1e-14
+
+
+def _energy(plan, c, V, w):
+    with torch.no_grad():
+        return ag.local_energy(plan, c, V, w).item()
+
+
+@pytest.mark.parametrize("name,grid,cell,ecut,k,nb", [GRAD_CASES[0], GRAD_CASES[2]])
+def test_finite_differences_16_directions(name, grid, cell, ecut, k, nb):
+    """Central differences, h = 1e-4, FP64, 16 random directions in c and in V."""
+    label(test="fd", name=name)
+    hkl = oracle.sphere_py(cell, ecut, k)
+    c = synth.coefficients(hkl, nb, k)
+    V = synth.potential(grid, 4)
+    w = synth.band_weights(nb)
+    plan = vloc.Plan(grid, cell, ecut, k)
+    tc, tV, tw = tensors(c, V, w, "f64")
+    E = ag.local_energy(plan, tc, tV, tw)
+    E.backward()
+    gc, gV = tc.grad.detach(), tV.grad.detach()
+    rng = np.random.default_rng(77)
+    h = 1e-4
+    for i in range(16):
+        d = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+        td = torch.from_numpy(d).cuda()
+        fd = (_energy(plan, tc.detach() + h * td, tV.detach(), tw.detach()) -
+              _energy(plan, tc.detach() - h * td, tV.detach(), tw.detach())) / (2 * h)
+        an = torch.sum(torch.real(torch.conj(gc) * td)).item()
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (i, fd, an)
+        u = torch.from_numpy(rng.standard_normal(V.shape)).cuda()
+        fdv = (_energy(plan, tc.detach(), tV.detach() + h * u, tw.detach()) -
+               _energy(plan, tc.detach(), tV.detach() - h * u, tw.detach())) / (2 * h)
+        anv = torch.sum(gV * u).item()
+        assert abs(fdv - anv) <= 1e-7 * max(1.0, abs(anv)), (i, fdv, anv)
+
+
+def test_grad_128_r32_512_bands_f32_with_f64_check():
+    """128^3, |G| <= 32 (137,065 PW), 512 bands: FP32 energy and gradients (FP64
+    reductions) against the FP64 path on the GPU; the FP64 path against the
+    oracle on sampled bands; FD on 4 directions in FP64."""
+    w_ = synth.WORKLOADS["c5_128"]
+    grid, cell, ecut = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"])
+    nb = w_["nbands"]
+    label(test="grad128", grid=grid, nb=nb)
+    hkl = oracle.sphere_py(cell, ecut)
+    assert hkl.shape[0] == 137065
+    c = synth.coefficients(hkl, nb)
+    V = synth.potential(grid, w_["ngauss"])
+    w = synth.band_weights(nb)
+    res = {}
+    for prec in ("f64", "f32"):
+        plan = vloc.Plan(grid, cell, ecut, precision=prec)
+        tc, tV, tw = tensors(c, V, w, prec)
+        E = ag.local_energy(plan, tc, tV, tw)
+        E.backward()
+        torch.cuda.synchronize()
+        res[prec] = (E.item(), tc.grad.cpu().numpy().astype(np.complex128),
+                     tV.grad.cpu().numpy().astype(np.float64).ravel(), plan, tc, tV, tw)
+        del E
+    E64, gc64, gV64 = res["f64"][:3]
+    E32, gc32, gV32 = res["f32"][:3]
+    errE, errc, errV = abs(E32 - E64) / abs(E64), relerr(gc32, gc64), relerr(gV32, gV64)
+    print("128^3 f32 vs f64: E", errE, "grad_c", errc, "grad_V", errV)
+    assert errE < 1e-5 and errc < 5e-6 and errV < 5e-6
+    sample = [0, 255, 511]
+    out = oracle.apply(grid, cell, ecut, (0, 0, 0), c[sample], V)
+    assert relerr(gc64[sample], 2 * w[sample, None] * out) < 1e-12
+    # FD (FP64) on 4 random directions
+    plan, tc, tV, tw = res["f64"][3:]
+    rng = np.random.default_rng(5)
+    h = 1e-4
+    for i in range(4):
+        d = torch.from_numpy(rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)).cuda()
+        fd = (_energy(plan, tc.detach() + h * d, tV.detach(), tw.detach()) -
+              _energy(plan, tc.detach() - h * d, tV.detach(), tw.detach())) / (2 * h)
+        an = float(np.sum(np.real(np.conj(gc64) * d.cpu().numpy())))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+        u = torch.from_numpy(rng.standard_normal(V.shape)).cuda()
+        fdv = (_energy(plan, tc.detach(), tV.detach() + h * u, tw.detach()) -
+               _energy(plan, tc.detach(), tV.detach() - h * u, tw.detach())) / (2 * h)
+        anv = float(np.dot(gV64, u.cpu().numpy().ravel()))
+        assert abs(fdv - anv) <= 1e-7 * max(1.0, abs(anv))

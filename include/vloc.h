@@ -182,6 +182,50 @@ vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r)
 /* c_out[n](g) = (1/N) sum_j exp(+2 pi i g.j/N) psi_r[n](j) for g in S. */
 vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_out);
 
+/* ------------------------------------------------------------- batches */
+/* Several k-points of one crystal (same grid, cell, ecut and options, each
+ * with its own cutoff sphere and band count) applied together: the bands of
+ * all k-points are concatenated (k-point order) and each band chunk runs as
+ * ONE launch of each kernel, whose workgroups take planes and stick groups of
+ * every k-point from one work list (the paper's balancing of uneven units,
+ * Sec. 3.2, carried to whole k-points; Sec. 1 on aggregating the transforms
+ * of many bands).  The members share one plane layout: each covers the union
+ * of the k-points' occupied x-planes, so a member's own results equal those
+ * of a stand-alone plan of the same k. */
+typedef struct vloc_batch_s *vloc_batch; /* opaque; owned by the library */
+
+/* nk in [1, 8]; kpts: nk*3 doubles (reduced coordinates, as for a plan).
+ * opt (NULL = defaults) applies to every member; its band_chunk counts bands
+ * over all k-points per launch (0 = all bands in one launch).  Errors as for
+ * vloc_plan_create_ex; on error *batch is NULL. */
+vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const double cell[9],
+                              double ecut, int32_t nk, const double *kpts,
+                              const vloc_options *opt);
+/* Waits for the batch's stream, frees the batch and its member plans. */
+vloc_status vloc_batch_destroy(vloc_batch batch);
+/* Borrowed handle of member ik (queries, and stand-alone calls on its own
+ * stream); valid until vloc_batch_destroy; vloc_plan_destroy refuses it. */
+vloc_status vloc_batch_plan(vloc_batch batch, int32_t ik, vloc_plan *plan);
+vloc_status vloc_batch_set_stream(vloc_batch batch, void *hip_stream);
+/* out[i][n] = V_loc c[i][n] for every k-point i < nk and band n < nbands[i].
+ * c, out: host arrays of nk device pointers ([nbands[i]][npw_i] complex of
+ * the batch precision; entries of k-points without bands may be NULL);
+ * nbands: host array of nk counts; V: device [N3][N2][N1] real.  No out may
+ * overlap V, any c or another out (VLOC_E_ALIAS).  Stream-ordered and
+ * asynchronous; calls on one batch must not run concurrently. */
+vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64_t *nbands,
+                             const void *V, void *const *out);
+/* With enable != 0, vloc_batch_apply records its launches once into a HIP
+ * graph (captured on a private stream) and replays it on the batch's stream
+ * while V, every c, out and band count stay the same; a change re-captures.
+ * Kernel timing is not recorded on the graph path. */
+vloc_status vloc_batch_use_graph(vloc_batch batch, int32_t enable);
+/* Timing of the eager path, as vloc_plan_enable_timing / read_timing. */
+vloc_status vloc_batch_enable_timing(vloc_batch batch, int32_t enable);
+vloc_status vloc_batch_read_timing(vloc_batch batch, double ms[3], int64_t launches[3]);
+/* out = {nk, band_chunk option, graphs captured, graph launches}. */
+vloc_status vloc_batch_info(vloc_batch batch, int64_t out[4]);
+
 /* Static description of a status code. */
 const char *vloc_status_string(vloc_status s);
 /* Message of the last failure on the calling thread ("" if none). */

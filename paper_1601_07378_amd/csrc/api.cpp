@@ -20,8 +20,11 @@
 
 using namespace vloc;
 
-struct vloc_plan_s {
-    HostPlan hp;
+// Device side shared by a plan and a batch: the tables of one or more member
+// plans (concatenated, one segment per member), the stick buffer, the
+// density partial planes and the timing events.
+struct Engine {
+    std::vector<const HostPlan *> members;
     hipStream_t stream = nullptr;
     bool uploaded = false;
     int device = -1;
@@ -30,16 +33,37 @@ struct vloc_plan_s {
     int2 *d_cols = nullptr;
     void *d_tw[3] = {nullptr, nullptr, nullptr};
     double2 *d_twx64 = nullptr;
+    std::vector<int> slot_off, group_off, col_off;
     void *d_S = nullptr;
     size_t S_bytes = 0;
     double *d_partial = nullptr; // density partial planes
     size_t partial_bytes = 0;
     Geometry geo{};
-    // kernel timing: events[4*i .. 4*i+3] bracket K1, K2, K3 of chunk launch i
+    // kernel timing: events[4*i .. 4*i+3] bracket K1, K2, K3 of launch i
     bool timing = false;
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
     std::vector<int> rec_modes;
+};
+
+struct vloc_plan_s {
+    HostPlan hp;
+    Engine eng;
+    bool borrowed = false; // member of a batch: freed with the batch
+};
+
+struct vloc_batch_s {
+    std::vector<vloc_plan_s *> plans; // members, owned
+    Engine eng;
+    int64_t band_chunk = 0;           // bands per launch over all k-points; 0 = all
+    // HIP graph of the last call's launches, replayed while the call's
+    // pointers and band counts stay the same
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> graph_key;
+    int64_t graphs_captured = 0, graph_launches = 0;
 };
 
 namespace {
@@ -58,92 +82,110 @@ vloc_status hip_fail(hipError_t e, const char *where)
     return VLOC_E_DEVICE;
 }
 
-void free_device(vloc_plan p)
+template <typename P>
+void free_ptr(P *&p)
 {
-    if (p->d_slot) (void)hipFree(p->d_slot);
-    if (p->d_groups) (void)hipFree(p->d_groups);
-    if (p->d_cols) (void)hipFree(p->d_cols);
-    if (p->d_twx64) (void)hipFree(p->d_twx64);
-    p->d_twx64 = nullptr;
-    p->d_cols = nullptr;
-    for (void *&t : p->d_tw)
-        if (t) (void)hipFree(t), t = nullptr;
-    if (p->d_S) (void)hipFree(p->d_S);
-    if (p->d_partial) (void)hipFree(p->d_partial);
-    p->d_partial = nullptr;
-    p->partial_bytes = 0;
-    p->d_slot = nullptr;
-    p->d_groups = nullptr;
-    p->d_S = nullptr;
-    p->S_bytes = 0;
-    p->uploaded = false;
+    if (p) (void)hipFree(p);
+    p = nullptr;
 }
 
-vloc_status upload(vloc_plan p)
+void free_device(Engine &E)
 {
-    if (p->uploaded) return VLOC_OK;
-    const HostPlan &h = p->hp;
+    free_ptr(E.d_slot);
+    free_ptr(E.d_groups);
+    free_ptr(E.d_cols);
+    free_ptr(E.d_twx64);
+    for (void *&t : E.d_tw) free_ptr(t);
+    free_ptr(E.d_S);
+    free_ptr(E.d_partial);
+    E.partial_bytes = 0;
+    E.S_bytes = 0;
+    E.uploaded = false;
+}
+
+// Waits for the engine's stream and frees everything it holds.
+void release(Engine &E)
+{
+    if (E.uploaded || E.d_S || !E.events.empty()) {
+        (void)hipStreamSynchronize(E.stream);
+        free_device(E);
+        for (hipEvent_t e : E.events) (void)hipEventDestroy(e);
+        E.events.clear();
+    }
+}
+
+template <typename V>
+hipError_t upload_vec(V *&dst, const std::vector<V> &src)
+{
+    hipError_t e = hipMalloc(&dst, sizeof(V) * std::max<size_t>(1, src.size()));
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice);
+}
+
+vloc_status upload(Engine &E)
+{
+    if (E.uploaded) return VLOC_OK;
+    const HostPlan &h = *E.members[0];
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev < 1) return fail(VLOC_E_DEVICE, "no HIP device available");
-    if ((e = hipGetDevice(&p->device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipGetDevice(&E.device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
 
-    const int64_t nst = h.nst();
-    std::vector<int4> slot(nst);
-    for (int64_t s = 0; s < nst; ++s) {
-        const Stick &st = h.sticks[h.stick_of_slot[s]];
-        int lm = st.lmin % h.grid[2];
-        if (lm < 0) lm += h.grid[2];
-        int kp = st.k % h.grid[1];
-        if (kp < 0) kp += h.grid[1];
-        slot[s] = make_int4(st.offset, st.count, lm, (st.h - h.hmin) * h.ldy + kp);
+    // member tables, concatenated: slots and groups relative to the member
+    std::vector<int4> slot;
+    std::vector<int2> groups, cols;
+    E.slot_off.clear();
+    E.group_off.clear();
+    E.col_off.clear();
+    int cap = 0;
+    for (const HostPlan *m : E.members) {
+        E.slot_off.push_back((int)slot.size());
+        E.group_off.push_back((int)groups.size());
+        E.col_off.push_back((int)cols.size());
+        for (int64_t s = 0; s < m->nst(); ++s) {
+            const Stick &st = m->sticks[m->stick_of_slot[s]];
+            int lm = st.lmin % m->grid[2];
+            if (lm < 0) lm += m->grid[2];
+            int kp = st.k % m->grid[1];
+            if (kp < 0) kp += m->grid[1];
+            slot.push_back(make_int4(st.offset, st.count, lm, (st.h - m->hmin) * m->ldy + kp));
+        }
+        for (int g = 0; g < m->ngroups; ++g) {
+            groups.push_back(make_int2(m->group_start[g], m->group_size[g]));
+            cap = std::max(cap, m->group_size[g]);
+        }
+        for (int c = 0; c < m->nxo; ++c) cols.push_back(make_int2(m->col_kmin[c], m->col_kcnt[c]));
     }
-    std::vector<int2> groups(h.ngroups);
-    for (int g = 0; g < h.ngroups; ++g) groups[g] = make_int2(h.group_start[g], h.group_size[g]);
-
-    std::vector<int2> cols(h.nxo);
-    for (int c = 0; c < h.nxo; ++c) cols[c] = make_int2(h.col_kmin[c], h.col_kcnt[c]);
-    if ((e = hipMalloc(&p->d_slot, sizeof(int4) * nst)) != hipSuccess) goto nomem;
-    if ((e = hipMalloc(&p->d_cols, sizeof(int2) * h.nxo)) != hipSuccess) goto nomem;
-    if ((e = hipMemcpy(p->d_cols, cols.data(), sizeof(int2) * h.nxo, hipMemcpyHostToDevice)) !=
-        hipSuccess)
-        goto devfail;
-    if ((e = hipMalloc(&p->d_groups, sizeof(int2) * h.ngroups)) != hipSuccess) goto nomem;
-    if ((e = hipMemcpy(p->d_slot, slot.data(), sizeof(int4) * nst, hipMemcpyHostToDevice)) !=
-        hipSuccess)
-        goto devfail;
-    if ((e = hipMemcpy(p->d_groups, groups.data(), sizeof(int2) * h.ngroups,
-                       hipMemcpyHostToDevice)) != hipSuccess)
-        goto devfail;
+    if ((e = upload_vec(E.d_slot, slot)) != hipSuccess) goto devfail;
+    if ((e = upload_vec(E.d_groups, groups)) != hipSuccess) goto devfail;
+    if ((e = upload_vec(E.d_cols, cols)) != hipSuccess) goto devfail;
     {
         const Split *sp[3] = {&h.sx, &h.sy, &h.sz};
         for (int a = 0; a < 3; ++a) {
             std::vector<double> t64 = twiddle_table(sp[a]->L);
-            size_t bytes;
-            const void *src;
-            std::vector<float> t32;
             if (h.opt.precision == VLOC_F32) {
-                t32.assign(t64.begin(), t64.end());
-                bytes = t32.size() * sizeof(float);
-                src = t32.data();
+                std::vector<float> t32(t64.begin(), t64.end());
+                float *d = nullptr;
+                e = upload_vec(d, t32);
+                E.d_tw[a] = d;
             } else {
-                bytes = t64.size() * sizeof(double);
-                src = t64.data();
+                double *d = nullptr;
+                e = upload_vec(d, t64);
+                E.d_tw[a] = d;
             }
-            if ((e = hipMalloc(&p->d_tw[a], bytes)) != hipSuccess) goto nomem;
-            if ((e = hipMemcpy(p->d_tw[a], src, bytes, hipMemcpyHostToDevice)) != hipSuccess)
-                goto devfail;
+            if (e != hipSuccess) goto devfail;
         }
     }
     {
         std::vector<double> t64 = twiddle_table(h.sx.L);
-        if ((e = hipMalloc(&p->d_twx64, t64.size() * sizeof(double))) != hipSuccess) goto nomem;
-        if ((e = hipMemcpy(p->d_twx64, t64.data(), t64.size() * sizeof(double),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-            goto devfail;
+        double *d = nullptr;
+        e = upload_vec(d, t64);
+        E.d_twx64 = reinterpret_cast<double2 *>(d);
+        if (e != hipSuccess) goto devfail;
     }
     {
-        Geometry &g = p->geo;
+        Geometry &g = E.geo;
         g.N1 = h.grid[0];
         g.N2 = h.grid[1];
         g.N3 = h.grid[2];
@@ -167,53 +209,45 @@ vloc_status upload(vloc_plan p)
         g.zy = h.zy;
         g.zz = h.zz;
         int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E.device) !=
                 hipSuccess ||
             cus < 1)
             cus = 256;
         const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, h.plane_lds)));
         g.resident_plane_wgs = cus * per_cu;
         g.nsub = 1;
-        g.nst = (int)nst;
-        g.npw = (int)h.npw();
-        g.ngroups = h.ngroups;
-        int cap = 0;
-        for (int s : h.group_size) cap = s > cap ? s : cap;
         g.group_cap = cap;
         g.inv_n = 1.0 / ((double)g.N1 * g.N2 * g.N3);
     }
-    p->uploaded = true;
+    E.uploaded = true;
     return VLOC_OK;
-nomem:
-    free_device(p);
-    (void)hipGetLastError();
-    return fail(VLOC_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
 devfail:
-    free_device(p);
+    free_device(E);
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory)
+        return fail(VLOC_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
     return hip_fail(e, "table upload");
 }
 
-vloc_status ensure_scratch(vloc_plan p, int64_t chunk)
+vloc_status ensure_scratch(Engine &E, size_t need)
 {
-    size_t need = (size_t)chunk * p->hp.grid[2] * (size_t)p->hp.nst() * p->hp.elem_bytes();
-    if (need <= p->S_bytes) return VLOC_OK;
+    if (need <= E.S_bytes) return VLOC_OK;
     const char *f = std::getenv("VLOC_TEST_FAIL_ALLOC");
     if (f && f[0] == '1') return fail(VLOC_E_NOMEM, "stick buffer allocation refused (test hook)");
-    if (p->d_S) {
-        hipError_t e = hipStreamSynchronize(p->stream);
+    if (E.d_S) {
+        hipError_t e = hipStreamSynchronize(E.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        (void)hipFree(p->d_S);
-        p->d_S = nullptr;
-        p->S_bytes = 0;
+        free_ptr(E.d_S);
+        E.S_bytes = 0;
     }
-    hipError_t e = hipMalloc(&p->d_S, need);
+    hipError_t e = hipMalloc(&E.d_S, need);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        p->d_S = nullptr;
+        E.d_S = nullptr;
         return fail(VLOC_E_NOMEM, "stick buffer allocation failed: " +
                                       std::string(hipGetErrorString(e)));
     }
-    p->S_bytes = need;
+    E.S_bytes = need;
     return VLOC_OK;
 }
 
@@ -223,81 +257,193 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb)
     return na && nb && x < y + nb && y < x + na;
 }
 
-DevTables tables(vloc_plan p)
+DevTables tables(const Engine &E)
 {
     DevTables t;
-    t.slot_info = p->d_slot;
-    t.groups = p->d_groups;
-    t.cols = p->d_cols;
-    t.twx = p->d_tw[0];
-    t.twy = p->d_tw[1];
-    t.twz = p->d_tw[2];
-    t.twx64 = p->d_twx64;
-    t.partial = p->d_partial;
+    t.slot_info = E.d_slot;
+    t.groups = E.d_groups;
+    t.cols = E.d_cols;
+    t.twx = E.d_tw[0];
+    t.twy = E.d_tw[1];
+    t.twz = E.d_tw[2];
+    t.twx64 = E.d_twx64;
+    t.partial = E.d_partial;
     t.wts = nullptr;
     return t;
 }
 
-// Next four events for one chunk (created on demand, reused after a read).
-hipError_t next_events(vloc_plan p, hipEvent_t *ev)
+// Next four events for one launch (created on demand, reused after a read).
+hipError_t next_events(Engine &E, hipEvent_t *ev)
 {
-    while (p->events.size() < p->events_used + 4) {
+    while (E.events.size() < E.events_used + 4) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
         if (r != hipSuccess) return r;
-        p->events.push_back(e);
+        E.events.push_back(e);
     }
-    for (int i = 0; i < 4; ++i) ev[i] = p->events[p->events_used + i];
-    p->events_used += 4;
+    for (int i = 0; i < 4; ++i) ev[i] = E.events[E.events_used + i];
+    E.events_used += 4;
     return hipSuccess;
 }
 
-template <typename T>
-vloc_status run_chunks(vloc_plan p, int mode, const void *in, int64_t nbands, const void *V,
-                       void *out, const double *wts = nullptr)
+// Band range [b0, b0 + nb) of one member, as a segment.
+struct Part {
+    int member;
+    int64_t b0;
+    int nb;
+};
+
+// The launches of one call: the caller's bands of every member, concatenated
+// in member order, cut into chunks of at most `chunk` bands; a chunk holds one
+// segment per member it touches.  Returns the stick-buffer bytes of the
+// largest chunk.
+size_t make_launches(const Engine &E, const void *const *in, void *const *out,
+                     const int64_t *nbands, int64_t chunk, std::vector<Launch> &ls)
 {
-    const HostPlan &h = p->hp;
-    const int64_t chunk = nbands < h.band_chunk ? nbands : h.band_chunk;
-    vloc_status s = ensure_scratch(p, chunk);
-    if (s != VLOC_OK) return s;
-    const Geometry &g = p->geo;
-    DevTables t = tables(p);
+    ls.clear();
+    const int nm = (int)E.members.size();
+    const int N3 = E.members[0]->grid[2];
+    size_t need = 0;
+    std::vector<Part> cur;
+    int64_t cur_bands = 0;
+    auto flush = [&]() {
+        if (cur.empty()) return;
+        Launch L{};
+        L.nseg = (int)cur.size();
+        long long s_off = 0;
+        int band_lo = 0, blk_lo = 0;
+        for (size_t i = 0; i < cur.size(); ++i) {
+            const Part &p = cur[i];
+            const HostPlan &m = *E.members[p.member];
+            const size_t es = (size_t)m.elem_bytes();
+            Seg &s = L.seg[i];
+            s.in = in ? static_cast<const char *>(in[p.member]) + p.b0 * m.npw() * es : nullptr;
+            s.out = out ? static_cast<char *>(out[p.member]) + p.b0 * m.npw() * es : nullptr;
+            s.s_off = s_off;
+            s.nst = (int)m.nst();
+            s.npw = (int)m.npw();
+            s.ngroups = m.ngroups;
+            s.slot_off = E.slot_off[p.member];
+            s.group_off = E.group_off[p.member];
+            s.col_off = E.col_off[p.member];
+            s.band_lo = band_lo;
+            s.nb = p.nb;
+            s.blk_lo = blk_lo;
+            s_off += (long long)p.nb * N3 * m.nst();
+            band_lo += p.nb;
+            blk_lo += p.nb * m.ngroups;
+        }
+        L.nbt = band_lo;
+        L.nblk = blk_lo;
+        need = std::max(need, (size_t)s_off * (size_t)E.members[0]->elem_bytes());
+        ls.push_back(L);
+        cur.clear();
+        cur_bands = 0;
+    };
+    for (int m = 0; m < nm; ++m) {
+        int64_t b = 0;
+        while (b < nbands[m]) {
+            int64_t take = std::min(nbands[m] - b, chunk - cur_bands);
+            cur.push_back(Part{m, b, (int)take});
+            cur_bands += take;
+            b += take;
+            if (cur_bands == chunk) flush();
+        }
+    }
+    flush();
+    return need;
+}
+
+// Enqueues K1 -> K2 -> K3 of every launch on stream st.  mode APPLY takes
+// V; G2R / R2G / DENSITY (one member) take psi / weights indexed from the
+// launch's first band.
+template <typename T>
+vloc_status run_launches(Engine &E, int mode, const std::vector<Launch> &ls, const void *V,
+                         void *psi, const double *wts, hipStream_t st, bool timed)
+{
+    const HostPlan &h = *E.members[0];
+    const Geometry &g = E.geo;
+    DevTables t = tables(E);
     t.wts = wts;
     hipError_t e;
-    for (int64_t b0 = 0; b0 < nbands; b0 += chunk) {
-        int nb = (int)((nbands - b0) < chunk ? (nbands - b0) : chunk);
+    int64_t band0 = 0;
+    for (const Launch &L : ls) {
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-        if (p->timing) {
-            if ((e = next_events(p, ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-            p->rec_modes.push_back(mode);
-            (void)hipEventRecord(ev[0], p->stream);
+        if (timed) {
+            if ((e = next_events(E, ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            E.rec_modes.push_back(mode);
+            (void)hipEventRecord(ev[0], st);
         }
         if (mode != MODE_R2G) {
-            e = launch_stick_fwd<T>(g, t, in, b0, nb, p->d_S, h.stick_threads, p->stream);
+            e = launch_stick_fwd<T>(g, t, L, E.d_S, h.stick_threads, st);
             if (e != hipSuccess) return hip_fail(e, "stick forward launch");
         }
-        if (p->timing) (void)hipEventRecord(ev[1], p->stream);
-        void *psi = mode == MODE_G2R ? out : (mode == MODE_R2G ? const_cast<void *>(in) : nullptr);
-        e = launch_plane<T>(g, t, mode, p->d_S, V, psi, b0, nb, h.plane_threads, h.plane_lds,
-                            p->stream);
+        if (timed) (void)hipEventRecord(ev[1], st);
+        e = launch_plane<T>(g, t, L, mode, E.d_S, V, psi, band0, h.plane_threads, h.plane_lds, st);
         if (e != hipSuccess) return hip_fail(e, "plane launch");
-        if (p->timing) (void)hipEventRecord(ev[2], p->stream);
+        if (timed) (void)hipEventRecord(ev[2], st);
         if (mode != MODE_G2R && mode != MODE_DENSITY) {
-            e = launch_stick_bwd<T>(g, t, p->d_S, out, b0, nb, h.stick_threads, p->stream);
+            e = launch_stick_bwd<T>(g, t, L, E.d_S, h.stick_threads, st);
             if (e != hipSuccess) return hip_fail(e, "stick backward launch");
         }
-        if (p->timing) (void)hipEventRecord(ev[3], p->stream);
+        if (timed) (void)hipEventRecord(ev[3], st);
+        band0 += L.nbt;
     }
     return VLOC_OK;
 }
 
+// One plan: its bands in chunks of the plan's band_chunk.
 vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, const void *V,
-                     void *out)
+                     void *out, const double *wts = nullptr)
 {
-    vloc_status s = upload(p);
+    Engine &E = p->eng;
+    vloc_status s = upload(E);
     if (s != VLOC_OK) return s;
-    if (p->hp.opt.precision == VLOC_F32) return run_chunks<float>(p, mode, in, nbands, V, out);
-    return run_chunks<double>(p, mode, in, nbands, V, out);
+    std::vector<Launch> ls;
+    const void *ins[1] = {mode == MODE_R2G ? nullptr : in};
+    void *outs[1] = {(mode == MODE_APPLY || mode == MODE_R2G) ? out : nullptr};
+    size_t need = make_launches(E, ins, outs, &nbands, p->hp.band_chunk, ls);
+    if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
+    void *psi = mode == MODE_G2R ? out : (mode == MODE_R2G ? const_cast<void *>(in) : nullptr);
+    if (p->hp.opt.precision == VLOC_F32)
+        return run_launches<float>(E, mode, ls, V, psi, wts, E.stream, E.timing);
+    return run_launches<double>(E, mode, ls, V, psi, wts, E.stream, E.timing);
+}
+
+vloc_status read_timing(Engine &E, double ms[3], int64_t launches[3])
+{
+    double acc[3] = {0, 0, 0};
+    int64_t cnt[3] = {0, 0, 0};
+    for (size_t i = 0; 4 * i + 3 < E.events_used; ++i) {
+        hipEvent_t *ev = &E.events[4 * i];
+        hipError_t e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        int mode = E.rec_modes[i];
+        for (int k = 0; k < 3; ++k) {
+            if ((k == 0 && mode == MODE_R2G) ||
+                (k == 2 && (mode == MODE_G2R || mode == MODE_DENSITY)))
+                continue;
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            acc[k] += t;
+            cnt[k] += 1;
+        }
+    }
+    E.events_used = 0;
+    E.rec_modes.clear();
+    if (ms) std::memcpy(ms, acc, sizeof acc);
+    if (launches) std::memcpy(launches, cnt, sizeof cnt);
+    return VLOC_OK;
+}
+
+void drop_graph(vloc_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
 }
 
 } // namespace
@@ -323,6 +469,7 @@ vloc_status vloc_plan_create_ex(vloc_plan *plan, const int32_t grid[3], const do
         delete p;
         return fail(s, err);
     }
+    p->eng.members.assign(1, &p->hp);
     *plan = p;
     g_err.clear();
     return VLOC_OK;
@@ -337,11 +484,8 @@ vloc_status vloc_plan_create(vloc_plan *plan, const int32_t grid[3], const doubl
 vloc_status vloc_plan_destroy(vloc_plan plan)
 {
     if (!plan) return VLOC_OK;
-    if (plan->uploaded || plan->d_S || !plan->events.empty()) {
-        (void)hipStreamSynchronize(plan->stream);
-        free_device(plan);
-        for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
-    }
+    if (plan->borrowed) return fail(VLOC_E_INVALID, "plan belongs to a batch");
+    release(plan->eng);
     delete plan;
     return VLOC_OK;
 }
@@ -349,7 +493,7 @@ vloc_status vloc_plan_destroy(vloc_plan plan)
 vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream)
 {
     if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
-    plan->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    plan->eng.stream = reinterpret_cast<hipStream_t>(hip_stream);
     return VLOC_OK;
 }
 
@@ -401,35 +545,14 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
 vloc_status vloc_plan_enable_timing(vloc_plan plan, int32_t enable)
 {
     if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
-    plan->timing = enable != 0;
+    plan->eng.timing = enable != 0;
     return VLOC_OK;
 }
 
 vloc_status vloc_plan_read_timing(vloc_plan plan, double ms[3], int64_t launches[3])
 {
     if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
-    double acc[3] = {0, 0, 0};
-    int64_t cnt[3] = {0, 0, 0};
-    for (size_t i = 0; 4 * i + 3 < plan->events_used; ++i) {
-        hipEvent_t *ev = &plan->events[4 * i];
-        hipError_t e = hipEventSynchronize(ev[3]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        int mode = plan->rec_modes[i];
-        for (int k = 0; k < 3; ++k) {
-            if ((k == 0 && mode == MODE_R2G) || (k == 2 && (mode == MODE_G2R || mode == MODE_DENSITY)))
-                continue;
-            float t = 0.f;
-            e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-            acc[k] += t;
-            cnt[k] += 1;
-        }
-    }
-    plan->events_used = 0;
-    plan->rec_modes.clear();
-    if (ms) std::memcpy(ms, acc, sizeof acc);
-    if (launches) std::memcpy(launches, cnt, sizeof cnt);
-    return VLOC_OK;
+    return read_timing(plan->eng, ms, launches);
 }
 
 vloc_status vloc_band_dot(vloc_plan plan, const void *a, const void *b, int64_t nbands, double *e)
@@ -438,11 +561,12 @@ vloc_status vloc_band_dot(vloc_plan plan, const void *a, const void *b, int64_t 
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!a || !b || !e) return fail(VLOC_E_INVALID, "NULL a, b or e");
-    vloc_status s = upload(plan);
+    vloc_status s = upload(plan->eng);
     if (s != VLOC_OK) return s;
+    hipStream_t st = plan->eng.stream;
     hipError_t err = plan->hp.opt.precision == VLOC_F32
-                         ? launch_band_dot<float>(a, b, plan->hp.npw(), nbands, e, plan->stream)
-                         : launch_band_dot<double>(a, b, plan->hp.npw(), nbands, e, plan->stream);
+                         ? launch_band_dot<float>(a, b, plan->hp.npw(), nbands, e, st)
+                         : launch_band_dot<double>(a, b, plan->hp.npw(), nbands, e, st);
     return err == hipSuccess ? VLOC_OK : hip_fail(err, "band dot launch");
 }
 
@@ -452,9 +576,9 @@ vloc_status vloc_weighted_sum(vloc_plan plan, const double *x, const double *w, 
     if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (!x || !w || !E) return fail(VLOC_E_INVALID, "NULL x, w or E");
-    vloc_status s = upload(plan);
+    vloc_status s = upload(plan->eng);
     if (s != VLOC_OK) return s;
-    hipError_t err = launch_weighted_sum(x, w, nbands, E, plan->stream);
+    hipError_t err = launch_weighted_sum(x, w, nbands, E, plan->eng.stream);
     return err == hipSuccess ? VLOC_OK : hip_fail(err, "weighted sum launch");
 }
 
@@ -465,13 +589,13 @@ vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, cons
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!x || !y) return fail(VLOC_E_INVALID, "NULL x or y");
-    vloc_status s = upload(plan);
+    vloc_status s = upload(plan->eng);
     if (s != VLOC_OK) return s;
     const int64_t npw = plan->hp.npw();
-    hipError_t err =
-        plan->hp.opt.precision == VLOC_F32
-            ? launch_scale_bands<float>(x, npw, nbands, w, scale, factor, y, plan->stream)
-            : launch_scale_bands<double>(x, npw, nbands, w, scale, factor, y, plan->stream);
+    hipStream_t st = plan->eng.stream;
+    hipError_t err = plan->hp.opt.precision == VLOC_F32
+                         ? launch_scale_bands<float>(x, npw, nbands, w, scale, factor, y, st)
+                         : launch_scale_bands<double>(x, npw, nbands, w, scale, factor, y, st);
     return err == hipSuccess ? VLOC_OK : hip_fail(err, "band scaling launch");
 }
 
@@ -483,10 +607,11 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
     if (nbands == 0) return VLOC_OK;
     if (!c || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, w or rho");
     if (plan->hp.plane_xq) return fail(VLOC_E_INVALID, "density needs the row-buffer x pass");
-    vloc_status s = upload(plan);
+    Engine &E = plan->eng;
+    vloc_status s = upload(E);
     if (s != VLOC_OK) return s;
     HostPlan &h = plan->hp;
-    Geometry &g = plan->geo;
+    Geometry &g = E.geo;
     const int64_t N = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
     const int64_t chunk = nbands < h.band_chunk ? nbands : h.band_chunk;
     // band subsets per launch: items N3 * nsub fill the resident workgroups in
@@ -508,30 +633,26 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
         g.nsub = (int)std::min<int64_t>(best, chunk);
     }
     const size_t need = (size_t)g.nsub * (size_t)N * sizeof(double);
-    if (need > plan->partial_bytes) {
-        if (plan->d_partial) {
-            hipError_t e = hipStreamSynchronize(plan->stream);
+    if (need > E.partial_bytes) {
+        if (E.d_partial) {
+            hipError_t e = hipStreamSynchronize(E.stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            (void)hipFree(plan->d_partial);
-            plan->d_partial = nullptr;
-            plan->partial_bytes = 0;
+            free_ptr(E.d_partial);
+            E.partial_bytes = 0;
         }
-        hipError_t e = hipMalloc(&plan->d_partial, need);
+        hipError_t e = hipMalloc(&E.d_partial, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            plan->d_partial = nullptr;
+            E.d_partial = nullptr;
             return fail(VLOC_E_NOMEM, "density buffer allocation failed");
         }
-        plan->partial_bytes = need;
+        E.partial_bytes = need;
     }
-    hipError_t e = launch_fill_f64(plan->d_partial, (int64_t)g.nsub * N, 0.0, plan->stream);
+    hipError_t e = launch_fill_f64(E.d_partial, (int64_t)g.nsub * N, 0.0, E.stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
-    s = h.opt.precision == VLOC_F32 ? run_chunks<float>(plan, MODE_DENSITY, c, nbands, nullptr,
-                                                        nullptr, w)
-                                    : run_chunks<double>(plan, MODE_DENSITY, c, nbands, nullptr,
-                                                         nullptr, w);
+    s = dispatch(plan, MODE_DENSITY, c, nbands, nullptr, nullptr, w);
     if (s != VLOC_OK) return s;
-    e = launch_density_reduce(plan->d_partial, g.nsub, N, g.inv_n, scale, rho, plan->stream);
+    e = launch_density_reduce(E.d_partial, g.nsub, N, g.inv_n, scale, rho, E.stream);
     return e == hipSuccess ? VLOC_OK : hip_fail(e, "density reduce launch");
 }
 
@@ -596,6 +717,232 @@ vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14])
                      h.plane_threads, h.plane_lds, h.nxo,        h.plane_xw,
                      h.plane_xq ? 2 : 1};
     std::memcpy(out, v, sizeof v);
+    return VLOC_OK;
+}
+
+/* ------------------------------------------------------------- batches */
+
+vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const double cell[9],
+                              double ecut, int32_t nk, const double *kpts,
+                              const vloc_options *opt)
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch pointer is NULL");
+    *batch = nullptr;
+    if (nk < 1 || nk > kMaxSeg) return fail(VLOC_E_INVALID, "nk must be in [1, 8]");
+    if (!kpts) return fail(VLOC_E_INVALID, "kpts is NULL");
+    vloc_batch b = new (std::nothrow) vloc_batch_s();
+    if (!b) return fail(VLOC_E_NOMEM, "host allocation failed");
+    std::string err;
+    vloc_status s = VLOC_OK;
+    try {
+        // pass 1: each k-point's own sphere and occupied ranges
+        Occupied u{};
+        for (int i = 0; i < nk && s == VLOC_OK; ++i) {
+            HostPlan h;
+            s = build_host_plan(h, grid, cell, ecut, kpts + 3 * i, opt, err);
+            if (s != VLOC_OK) break;
+            if (i == 0) u = Occupied{h.hmin, h.hmax, h.kmin, h.kmax, h.lmin, h.lmax};
+            u.hmin = std::min(u.hmin, h.hmin);
+            u.hmax = std::max(u.hmax, h.hmax);
+            u.kmin = std::min(u.kmin, h.kmin);
+            u.kmax = std::max(u.kmax, h.kmax);
+            u.lmin = std::min(u.lmin, h.lmin);
+            u.lmax = std::max(u.lmax, h.lmax);
+        }
+        // pass 2: every member laid out on the union of the ranges
+        for (int i = 0; i < nk && s == VLOC_OK; ++i) {
+            vloc_plan p = new vloc_plan_s();
+            p->borrowed = true;
+            b->plans.push_back(p);
+            s = build_host_plan(p->hp, grid, cell, ecut, kpts + 3 * i, opt, err, &u);
+            p->eng.members.assign(1, &p->hp);
+        }
+        if (s == VLOC_OK) {
+            const HostPlan &h0 = b->plans[0]->hp;
+            for (vloc_plan p : b->plans) {
+                const HostPlan &h = p->hp;
+                if (h.nxo != h0.nxo || h.hmin != h0.hmin || h.zx != h0.zx || h.zy != h0.zy ||
+                    h.zz != h0.zz || h.plane_lds != h0.plane_lds || h.plane_xw != h0.plane_xw ||
+                    h.plane_rb != h0.plane_rb || h.plane_xq != h0.plane_xq) {
+                    s = VLOC_E_INVALID;
+                    err = "internal: batch members disagree on the plane layout";
+                }
+            }
+            for (vloc_plan p : b->plans) b->eng.members.push_back(&p->hp);
+            b->band_chunk = opt ? opt->band_chunk : 0;
+        }
+    } catch (const std::bad_alloc &) {
+        s = VLOC_E_NOMEM;
+        err = "host allocation failed";
+    }
+    if (s != VLOC_OK) {
+        for (vloc_plan p : b->plans) delete p;
+        delete b;
+        return fail(s, err);
+    }
+    *batch = b;
+    g_err.clear();
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_destroy(vloc_batch batch)
+{
+    if (!batch) return VLOC_OK;
+    (void)hipStreamSynchronize(batch->eng.stream);
+    drop_graph(batch);
+    if (batch->cap_stream) (void)hipStreamDestroy(batch->cap_stream);
+    release(batch->eng);
+    for (vloc_plan p : batch->plans) {
+        release(p->eng);
+        delete p;
+    }
+    delete batch;
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_plan(vloc_batch batch, int32_t ik, vloc_plan *plan)
+{
+    if (!batch || !plan) return fail(VLOC_E_INVALID, "NULL argument");
+    if (ik < 0 || ik >= (int32_t)batch->plans.size()) return fail(VLOC_E_INVALID, "ik out of range");
+    *plan = batch->plans[ik];
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_set_stream(vloc_batch batch, void *hip_stream)
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
+    batch->eng.stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_use_graph(vloc_batch batch, int32_t enable)
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
+    batch->use_graph = enable != 0;
+    if (!batch->use_graph) {
+        (void)hipStreamSynchronize(batch->eng.stream);
+        drop_graph(batch);
+    }
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64_t *nbands,
+                             const void *V, void *const *out)
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
+    if (!c || !nbands || !out) return fail(VLOC_E_INVALID, "NULL c, nbands or out array");
+    const int nk = (int)batch->plans.size();
+    const HostPlan &h0 = batch->plans[0]->hp;
+    const size_t es = (size_t)h0.elem_bytes();
+    const size_t vbytes = (size_t)h0.grid[0] * h0.grid[1] * h0.grid[2] * (es / 2);
+    int64_t total = 0;
+    for (int i = 0; i < nk; ++i) {
+        if (nbands[i] < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+        total += nbands[i];
+    }
+    if (total == 0) return VLOC_OK;
+    if (!V) return fail(VLOC_E_INVALID, "V is NULL");
+    if ((uintptr_t)V % (es / 2)) return fail(VLOC_E_INVALID, "misaligned V");
+    for (int i = 0; i < nk; ++i) {
+        if (!nbands[i]) continue;
+        if (!c[i] || !out[i]) return fail(VLOC_E_INVALID, "NULL c or out of a k-point with bands");
+        if (((uintptr_t)c[i] | (uintptr_t)out[i]) % es)
+            return fail(VLOC_E_INVALID, "misaligned c or out");
+        const size_t ob = (size_t)nbands[i] * (size_t)batch->plans[i]->hp.npw() * es;
+        if (overlaps(out[i], ob, V, vbytes)) return fail(VLOC_E_ALIAS, "out overlaps V");
+        for (int j = 0; j < nk; ++j) {
+            if (!nbands[j]) continue;
+            const size_t cb = (size_t)nbands[j] * (size_t)batch->plans[j]->hp.npw() * es;
+            if (overlaps(out[i], ob, c[j], cb)) return fail(VLOC_E_ALIAS, "out overlaps a c");
+            if (j != i && overlaps(out[i], ob, out[j], cb))
+                return fail(VLOC_E_ALIAS, "two outputs overlap");
+        }
+    }
+    Engine &E = batch->eng;
+    vloc_status s = upload(E);
+    if (s != VLOC_OK) return s;
+    int maxg = 1;
+    for (vloc_plan p : batch->plans) maxg = std::max(maxg, p->hp.ngroups);
+    int64_t chunk = batch->band_chunk > 0 ? batch->band_chunk : total;
+    chunk = std::min<int64_t>(chunk, INT32_MAX / maxg);
+    chunk = std::min<int64_t>(chunk, INT32_MAX / h0.grid[2]);
+    std::vector<Launch> ls;
+    size_t need = make_launches(E, c, out, nbands, chunk, ls);
+    if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
+    const bool f32 = h0.opt.precision == VLOC_F32;
+    if (!batch->use_graph) {
+        return f32 ? run_launches<float>(E, MODE_APPLY, ls, V, nullptr, nullptr, E.stream, E.timing)
+                   : run_launches<double>(E, MODE_APPLY, ls, V, nullptr, nullptr, E.stream,
+                                          E.timing);
+    }
+    // graph path: capture the launches once per set of pointers and counts
+    std::vector<uintptr_t> key;
+    key.push_back((uintptr_t)V);
+    key.push_back((uintptr_t)E.d_S);
+    for (int i = 0; i < nk; ++i) {
+        key.push_back((uintptr_t)c[i]);
+        key.push_back((uintptr_t)out[i]);
+        key.push_back((uintptr_t)nbands[i]);
+    }
+    hipError_t e;
+    if (!batch->exec || key != batch->graph_key) {
+        if (batch->exec) {
+            if ((e = hipStreamSynchronize(E.stream)) != hipSuccess)
+                return hip_fail(e, "hipStreamSynchronize");
+        }
+        drop_graph(batch);
+        if (!batch->cap_stream &&
+            (e = hipStreamCreateWithFlags(&batch->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(batch->cap_stream, hipStreamCaptureModeRelaxed)) !=
+            hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        s = f32 ? run_launches<float>(E, MODE_APPLY, ls, V, nullptr, nullptr, batch->cap_stream,
+                                      false)
+                : run_launches<double>(E, MODE_APPLY, ls, V, nullptr, nullptr, batch->cap_stream,
+                                       false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(batch->cap_stream, &g);
+        if (s != VLOC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        batch->graph = g;
+        if ((e = hipGraphInstantiateWithFlags(&batch->exec, g, 0)) != hipSuccess) {
+            batch->exec = nullptr;
+            drop_graph(batch);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        batch->graph_key = key;
+        batch->graphs_captured++;
+    }
+    if ((e = hipGraphLaunch(batch->exec, E.stream)) != hipSuccess)
+        return hip_fail(e, "hipGraphLaunch");
+    batch->graph_launches++;
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_enable_timing(vloc_batch batch, int32_t enable)
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
+    batch->eng.timing = enable != 0;
+    return VLOC_OK;
+}
+
+vloc_status vloc_batch_read_timing(vloc_batch batch, double ms[3], int64_t launches[3])
+{
+    if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
+    return read_timing(batch->eng, ms, launches);
+}
+
+vloc_status vloc_batch_info(vloc_batch batch, int64_t out[4])
+{
+    if (!batch || !out) return fail(VLOC_E_INVALID, "NULL argument");
+    out[0] = (int64_t)batch->plans.size();
+    out[1] = batch->band_chunk;
+    out[2] = batch->graphs_captured;
+    out[3] = batch->graph_launches;
     return VLOC_OK;
 }
 

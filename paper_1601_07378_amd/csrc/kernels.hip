@@ -107,21 +107,52 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
     }
 }
 
+// Segment of a launch by a uniform key (stick-kernel block or launch band):
+// the last segment whose first key is <= v.  Fields are copied with
+// compile-time indices so that the descriptor stays in scalar registers.
+__device__ __forceinline__ Seg seg_by_block(const Launch &L, int v)
+{
+    Seg r = L.seg[0];
+#pragma unroll
+    for (int i = 1; i < kMaxSeg; ++i)
+        if (i < L.nseg && v >= L.seg[i].blk_lo) r = L.seg[i];
+    return r;
+}
+__device__ __forceinline__ int seg_index_by_band(const Launch &L, int v)
+{
+    int s = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxSeg; ++i)
+        if (i < L.nseg && v >= L.seg[i].band_lo) s = i;
+    return s;
+}
+__device__ __forceinline__ Seg seg_at(const Launch &L, int s)
+{
+    Seg r = L.seg[0];
+#pragma unroll
+    for (int i = 1; i < kMaxSeg; ++i)
+        if (i == s) r = L.seg[i];
+    return r;
+}
+
 // ------------------------------------------------------------------ K1
-// One workgroup per (stick group, band).  Stage A loads c straight from HBM
-// (only the stick's own run is non-zero), stage B writes the z-transformed
-// stick to S[band][z][slot]; lanes of consecutive sticks write consecutive
-// slots.
+// One workgroup per (stick group, band) of a segment.  Stage A loads c
+// straight from HBM (only the stick's own run is non-zero), stage B writes the
+// z-transformed stick to S[band][z][slot]; lanes of consecutive sticks write
+// consecutive slots.
 template <typename T, int CZ1, int CZ2, int ZZ>
-__global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t,
-                                                   const cx<T> *__restrict__ c,
-                                                   cx<T> *__restrict__ S, long long band0)
+__global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Launch L,
+                                                   cx<T> *__restrict__ S)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *lines = reinterpret_cast<cx<T> *>(smem_raw);
-    const int2 gi = t.groups[blockIdx.x];
-    const int s0 = gi.x, ns = gi.y, bl = blockIdx.y;
-    const cx<T> *cb = c + (band0 + bl) * (long long)g.npw;
+    const Seg sg = seg_by_block(L, blockIdx.x);
+    const int rb = blockIdx.x - sg.blk_lo;
+    const int bl = rb / sg.ngroups, gr = rb - bl * sg.ngroups;
+    const int2 gi = t.groups[sg.group_off + gr];
+    const int s0 = gi.x, ns = gi.y;
+    const int4 *slot_info = t.slot_info + sg.slot_off;
+    const cx<T> *cb = reinterpret_cast<const cx<T> *>(sg.in) + bl * (long long)sg.npw;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
     const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
     const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
@@ -130,7 +161,7 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t,
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L2; task += blockDim.x) {
             const int j = task / L2, n2 = task - j * L2;
-            const int4 si = t.slot_info[s0 + j];
+            const int4 si = slot_info[s0 + j];
             T xr[R], xi[R];
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
@@ -164,10 +195,10 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t,
                 xi[n2] = v.y;
             }
             Dft<R, -1, T>::run(xr, xi);
-            cx<T> *Sb = S + (long long)bl * N3 * g.nst + s0 + j;
+            cx<T> *Sb = S + sg.s_off + (long long)bl * N3 * sg.nst + s0 + j;
 #pragma unroll
             for (int k2 = 0; k2 < R; ++k2)
-                Sb[(long long)(k1 + L1 * k2) * g.nst] = mk<T>(xr[k2], xi[k2]);
+                Sb[(long long)(k1 + L1 * k2) * sg.nst] = mk<T>(xr[k2], xi[k2]);
         }
     });
 }
@@ -176,15 +207,18 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t,
 // Mirror of K1: stage B' reads S[band][z][slot] (coalesced over sticks), stage
 // A' keeps only the stick's own run, scales by 1/N and writes out.
 template <typename T, int CZ1, int CZ2, int ZZ>
-__global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t,
-                                                   const cx<T> *__restrict__ S,
-                                                   cx<T> *__restrict__ out, long long band0)
+__global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Launch L,
+                                                   const cx<T> *__restrict__ S)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *lines = reinterpret_cast<cx<T> *>(smem_raw);
-    const int2 gi = t.groups[blockIdx.x];
-    const int s0 = gi.x, ns = gi.y, bl = blockIdx.y;
-    cx<T> *ob = out + (band0 + bl) * (long long)g.npw;
+    const Seg sg = seg_by_block(L, blockIdx.x);
+    const int rb = blockIdx.x - sg.blk_lo;
+    const int bl = rb / sg.ngroups, gr = rb - bl * sg.ngroups;
+    const int2 gi = t.groups[sg.group_off + gr];
+    const int s0 = gi.x, ns = gi.y;
+    const int4 *slot_info = t.slot_info + sg.slot_off;
+    cx<T> *ob = reinterpret_cast<cx<T> *>(sg.out) + bl * (long long)sg.npw;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
     const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
     const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
@@ -194,11 +228,11 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t,
         constexpr int R = decltype(RC)::value;
         for (int task = threadIdx.x; task < ns * L1; task += blockDim.x) {
             const int k1 = task / ns, j = task - k1 * ns;
-            const cx<T> *Sb = S + (long long)bl * N3 * g.nst + s0 + j;
+            const cx<T> *Sb = S + sg.s_off + (long long)bl * N3 * sg.nst + s0 + j;
             T xr[R], xi[R];
 #pragma unroll
             for (int k2 = 0; k2 < R; ++k2) {
-                cx<T> v = Sb[(long long)(k1 + L1 * k2) * g.nst];
+                cx<T> v = Sb[(long long)(k1 + L1 * k2) * sg.nst];
                 xr[k2] = v.x;
                 xi[k2] = v.y;
             }
@@ -223,7 +257,7 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t,
             }
             twiddle<R, +1, T>(xr, xi, n2, tw);
             Dft<R, +1, T>::run(xr, xi);
-            const int4 si = t.slot_info[s0 + j];
+            const int4 si = slot_info[s0 + j];
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
                 if (masked<ZZ>(n1)) continue;
@@ -412,9 +446,9 @@ __device__ __forceinline__ void quad_twiddle(T *xr, T *xi, int q, int L,
 }
 
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY, int XQ>
-__device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t,
+__device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t, const Launch &L,
                                            cx<T> *__restrict__ S, const T *__restrict__ V,
-                                           cx<T> *__restrict__ psi, long long band0, int nb)
+                                           cx<T> *__restrict__ psi, long long band0)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem_raw);
@@ -435,7 +469,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
 
     const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
     const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
-    const int nst = g.nst;
+    const int nb = L.nbt;
 
     // Work items: a plane (z, band) for the transforms; for the density a
     // (z, band subset) pair whose bands this workgroup runs one after another,
@@ -480,24 +514,36 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             k = bps; // rest of this subset is empty: go to the next item
         }
     };
+    // Segment of a launch band (the density runs one segment).
+    auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
     // The first PF slots of this thread keep their plane positions in
-    // registers for the whole kernel, and their values for the next plane are
-    // loaded while the current plane is transformed.
+    // registers while consecutive planes belong to one segment, and their
+    // values for the next plane are loaded while the current plane is
+    // transformed.
     constexpr int PF = 4;
     int spos[PF];
     cx<T> sval[PF];
-#pragma unroll
-    for (int i = 0; i < PF; ++i) {
-        const int sl = tid + i * nthr;
-        spos[i] = sl < nst ? t.slot_info[sl].w : 0;
-        sval[i] = mk<T>(T(0), T(0));
-    }
-    auto prefetch = [&](int zz, int bb) {
-        const cx<T> *Sj = S + ((long long)bb * g.N3 + zz) * nst;
+    int spos_seg = -1;
+    auto load_pos = [&](int si) {
+        const Seg sg = seg_at(L, si);
+        const int4 *sl_info = t.slot_info + sg.slot_off;
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int sl = tid + i * nthr;
-            if (sl < nst) sval[i] = Sj[sl];
+            spos[i] = sl < sg.nst ? sl_info[sl].w : 0;
+        }
+        spos_seg = si;
+    };
+#pragma unroll
+    for (int i = 0; i < PF; ++i) sval[i] = mk<T>(T(0), T(0));
+    load_pos(0);
+    auto prefetch = [&](int zz, int bb) {
+        const Seg sg = seg_at(L, seg_of(bb));
+        const cx<T> *Sj = S + sg.s_off + ((long long)(bb - sg.band_lo) * g.N3 + zz) * sg.nst;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            if (sl < sg.nst) sval[i] = Sj[sl];
         }
     };
     int jc = j0, kc = 0;
@@ -516,7 +562,13 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     for (; have; have = advance(jc, kc)) {
     int z, bl;
     plane_of(jc, kc, z, bl);
-    cx<T> *Sz = S + ((long long)bl * g.N3 + z) * nst;
+    const int si = seg_of(bl);
+    const Seg sg = seg_at(L, si);
+    const int nst = sg.nst;
+    const int4 *slots = t.slot_info + sg.slot_off;
+    const int2 *cols = t.cols + sg.col_off;
+    cx<T> *Sz = S + sg.s_off + ((long long)(bl - sg.band_lo) * g.N3 + z) * nst;
+    if (si != spos_seg) load_pos(si);
     cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
     const T *Vz = V ? V + (long long)z * N2 * N1 : nullptr;
     double *accz = DENS ? t.partial + ((long long)(bl / bps) * g.N3 + z) * N2 * N1 : nullptr;
@@ -525,7 +577,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
 #pragma unroll
         for (int i = 0; i < PF; ++i)
             if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
-        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[t.slot_info[sl].w] = Sz[sl];
+        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
         __syncthreads();
         {
             int jn = jc, kn = kc, zz, bb;
@@ -539,7 +591,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L2y; task += nthr) {
                 const int n2 = task / nxo, hc = task - n2 * nxo;
-                const int2 ci = t.cols[hc];
+                const int2 ci = cols[hc];
                 cx<T> *col = plane + hc * ldy + n2;
                 T xr[R], xi[R];
 #pragma unroll
@@ -784,7 +836,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
             const int n2 = task / nxo, hc = task - n2 * nxo;
-            const int2 ci = t.cols[hc];
+            const int2 ci = cols[hc];
             cx<T> *col = plane + hc * ldy + n2;
             T xr[R], xi[R];
 #pragma unroll
@@ -808,28 +860,28 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
 #pragma unroll
     for (int i = 0; i < PF; ++i)
         if (tid + i * nthr < nst) Sz[tid + i * nthr] = plane[spos[i]];
-    for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = plane[t.slot_info[sl].w];
+    for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = plane[slots[sl].w];
     __syncthreads(); // the next plane's scatter overwrites P
     }
 }
 
 // LDS row-buffer variant (any split), up to 512 threads.
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY>
-__global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, cx<T> *__restrict__ S,
-                                               const T *__restrict__ V,
-                                               cx<T> *__restrict__ psi, long long band0, int nb)
+__global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, Launch L,
+                                               cx<T> *__restrict__ S, const T *__restrict__ V,
+                                               cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0>(g, t, S, V, psi, band0, nb);
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0>(g, t, L, S, V, psi, band0);
 }
 
 // Quad variant: no row buffer, so the occupied plane is the only LDS and two
 // workgroups fit on a CU even in FP64; 3 waves per SIMD bound the registers.
 template <typename T, int MODE, int XQ, int CY1, int CY2>
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3)))
-void k_plane_quad(Geometry g, DevTables t, cx<T> *__restrict__ S, const T *__restrict__ V,
-                  cx<T> *__restrict__ psi, long long band0, int nb)
+void k_plane_quad(Geometry g, DevTables t, Launch L, cx<T> *__restrict__ S,
+                  const T *__restrict__ V, cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ>(g, t, S, V, psi, band0, nb);
+    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ>(g, t, L, S, V, psi, band0);
 }
 
 // ------------------------------------------------------------ launchers
@@ -857,20 +909,19 @@ static hipError_t allow_lds(K kernel, size_t bytes)
 // kernels; any other plan runs the same kernels with runtime sizes.
 #define VLOC_STICK_SPECS(X)                                                                       \
     X(8, 12, 0x38) X(8, 12, 0) X(4, 6, 0x4) X(4, 6, 0) X(8, 16, 0x38) X(8, 16, 0)               \
-    X(8, 10, 0x38) X(8, 10, 0)
+    X(8, 10, 0x38) X(8, 10, 0) X(8, 16, 0x3C)
 
 template <typename T>
-hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const void *c, int64_t band0,
-                            int nb, void *S, int threads, hipStream_t st)
+hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                            int threads, hipStream_t st)
 {
-    if (nb <= 0) return hipSuccess;
+    if (L.nblk <= 0) return hipSuccess;
     size_t lds = (size_t)g.group_cap * g.ldz * sizeof(cx<T>);
     auto go = [&](auto kern) {
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
-                           reinterpret_cast<const cx<T> *>(c), reinterpret_cast<cx<T> *>(S),
-                           (long long)band0);
+        hipLaunchKernelGGL(kern, dim3(L.nblk), dim3(threads), lds, st, g, t, L,
+                           reinterpret_cast<cx<T> *>(S));
         return hipGetLastError();
     };
 #define VLOC_K1(A, B, Z)                                                                           \
@@ -881,17 +932,16 @@ hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const void *c
 }
 
 template <typename T>
-hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S, void *out,
-                            int64_t band0, int nb, int threads, hipStream_t st)
+hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch &L, const void *S,
+                            int threads, hipStream_t st)
 {
-    if (nb <= 0) return hipSuccess;
+    if (L.nblk <= 0) return hipSuccess;
     size_t lds = (size_t)g.group_cap * g.ldz * sizeof(cx<T>);
     auto go = [&](auto kern) {
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(g.ngroups, nb), dim3(threads), lds, st, g, t,
-                           reinterpret_cast<const cx<T> *>(S), reinterpret_cast<cx<T> *>(out),
-                           (long long)band0);
+        hipLaunchKernelGGL(kern, dim3(L.nblk), dim3(threads), lds, st, g, t, L,
+                           reinterpret_cast<const cx<T> *>(S));
         return hipGetLastError();
     };
 #define VLOC_K3(A, B, Z)                                                                           \
@@ -902,44 +952,44 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S
 }
 
 template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int ZY>
-static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, void *S, const void *V,
-                                     void *psi, int64_t band0, int nb, int threads, int lds,
-                                     hipStream_t st)
+static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, const Launch &L,
+                                     void *S, const void *V, void *psi, int64_t band0,
+                                     int threads, int lds, hipStream_t st)
 {
     auto kern = k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>;
     hipError_t e = allow_lds(kern, (size_t)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, nb)), dim3(threads), (size_t)lds, st, g, t,
-                       reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
-                       reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
+    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g, t,
+                       L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                       reinterpret_cast<cx<T> *>(psi), (long long)band0);
     return hipGetLastError();
 }
 
 template <typename T, int MODE, int XQ, int Y1, int Y2>
-static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, void *S, const void *V,
-                                    void *psi, int64_t band0, int nb, int threads, int lds,
-                                    hipStream_t st)
+static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, const Launch &L,
+                                    void *S, const void *V, void *psi, int64_t band0,
+                                    int threads, int lds, hipStream_t st)
 {
     auto kern = k_plane_quad<T, MODE, XQ, Y1, Y2>;
     hipError_t e = allow_lds(kern, (size_t)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, nb)), dim3(threads), (size_t)lds, st, g, t,
-                       reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
-                       reinterpret_cast<cx<T> *>(psi), (long long)band0, nb);
+    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g, t,
+                       L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                       reinterpret_cast<cx<T> *>(psi), (long long)band0);
     return hipGetLastError();
 }
 
 // Specialised line splits for the common grids; any other split runs the same
 // kernel with runtime sizes.
 template <typename T, int MODE>
-static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void *S, const void *V,
-                                    void *psi, int64_t band0, int nb, int threads, int lds,
-                                    hipStream_t st)
+static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const Launch &L,
+                                    void *S, const void *V, void *psi, int64_t band0,
+                                    int threads, int lds, hipStream_t st)
 {
     if constexpr (MODE != MODE_DENSITY) if (g.xq) {
 #define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
         if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
-            return launch_plane_quad<T, MODE, XQ, Y1, Y2>(g, t, S, V, psi, band0, nb, threads,    \
+            return launch_plane_quad<T, MODE, XQ, Y1, Y2>(g, t, L, S, V, psi, band0, threads,     \
                                                            lds, st);
         VLOC_QUAD_CASE(24, 8, 12)
         VLOC_QUAD_CASE(6, 4, 6)
@@ -950,7 +1000,7 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void 
     }
 #define VLOC_PLANE_CASE(X1, X2, Y1, Y2, ZX, ZY)                                                    \
     if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && g.zx == ZX && g.zy == ZY)     \
-        return launch_plane_sized<T, MODE, X1, X2, Y1, Y2, ZX, ZY>(g, t, S, V, psi, band0, nb,    \
+        return launch_plane_sized<T, MODE, X1, X2, Y1, Y2, ZX, ZY>(g, t, L, S, V, psi, band0,     \
                                                                    threads, lds, st);
     VLOC_PLANE_CASE(8, 12, 8, 12, 0x38, 0x38)
     VLOC_PLANE_CASE(8, 12, 8, 12, 0, 0)
@@ -961,38 +1011,41 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, void 
     VLOC_PLANE_CASE(8, 10, 8, 10, 0x38, 0x38)
     VLOC_PLANE_CASE(8, 10, 8, 10, 0, 0)
     VLOC_PLANE_CASE(8, 9, 8, 12, 0, 0)
+    VLOC_PLANE_CASE(8, 9, 8, 12, 0x38, 0x3C)
 #undef VLOC_PLANE_CASE
-    return launch_plane_sized<T, MODE, 0, 0, 0, 0, 0, 0>(g, t, S, V, psi, band0, nb, threads, lds, st);
+    return launch_plane_sized<T, MODE, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads, lds,
+                                                         st);
 }
 
 template <typename T>
-hipError_t launch_plane(const Geometry &g, const DevTables &t, int mode, void *S, const void *V,
-                        void *psi, int64_t band0, int nb, int threads, int lds_bytes,
+hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, int mode, void *S,
+                        const void *V, void *psi, int64_t band0, int threads, int lds_bytes,
                         hipStream_t st)
 {
-    if (nb <= 0) return hipSuccess;
+    if (L.nbt <= 0) return hipSuccess;
+    if (mode != MODE_APPLY && L.nseg != 1) return hipErrorInvalidValue;
     switch (mode) {
     case MODE_APPLY:
-        return launch_plane_mode<T, MODE_APPLY>(g, t, S, V, psi, band0, nb, threads, lds_bytes, st);
+        return launch_plane_mode<T, MODE_APPLY>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
     case MODE_G2R:
-        return launch_plane_mode<T, MODE_G2R>(g, t, S, V, psi, band0, nb, threads, lds_bytes, st);
+        return launch_plane_mode<T, MODE_G2R>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
     case MODE_R2G:
-        return launch_plane_mode<T, MODE_R2G>(g, t, S, V, psi, band0, nb, threads, lds_bytes, st);
+        return launch_plane_mode<T, MODE_R2G>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
     case MODE_DENSITY:
         if (g.xq) return hipErrorInvalidValue; // density runs on the row-buffer x pass only
-        return launch_plane_mode<T, MODE_DENSITY>(g, t, S, V, psi, band0, nb, threads, lds_bytes,
+        return launch_plane_mode<T, MODE_DENSITY>(g, t, L, S, V, psi, band0, threads, lds_bytes,
                                                   st);
     default: return hipErrorInvalidValue;
     }
 }
 
 #define VLOC_INSTANTIATE(T)                                                                       \
-    template hipError_t launch_stick_fwd<T>(const Geometry &, const DevTables &, const void *,   \
-                                            int64_t, int, void *, int, hipStream_t);             \
-    template hipError_t launch_stick_bwd<T>(const Geometry &, const DevTables &, const void *,   \
-                                            void *, int64_t, int, int, hipStream_t);             \
-    template hipError_t launch_plane<T>(const Geometry &, const DevTables &, int, void *,         \
-                                        const void *, void *, int64_t, int, int, int,            \
+    template hipError_t launch_stick_fwd<T>(const Geometry &, const DevTables &, const Launch &, \
+                                            void *, int, hipStream_t);                           \
+    template hipError_t launch_stick_bwd<T>(const Geometry &, const DevTables &, const Launch &, \
+                                            const void *, int, hipStream_t);                     \
+    template hipError_t launch_plane<T>(const Geometry &, const DevTables &, const Launch &, int, \
+                                        void *, const void *, void *, int64_t, int, int,         \
                                         hipStream_t);
 VLOC_INSTANTIATE(double)
 VLOC_INSTANTIATE(float)

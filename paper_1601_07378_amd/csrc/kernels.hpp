@@ -31,20 +31,43 @@ struct Geometry {
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
     int resident_plane_wgs; // plane workgroups resident at once on the device
     int nsub;       // density: band subsets per launch
-    int nst, npw, ngroups;
-    int group_cap;  // most sticks in one group
+    int group_cap;  // most sticks in one group (over all segments)
     double inv_n;   // 1 / (N1 N2 N3)
 };
 
-// K1: stick z-transforms (G -> r direction) from c into the stick buffer S.
-// S layout: [band][z][slot].
+// One launch covers the bands of up to kMaxSeg k-points ("segments") that
+// share the grid and the occupied-plane geometry.  Segment s owns launch bands
+// [band_lo, band_lo + nb), its stick buffer at S + s_off ([band][z][slot],
+// nst slots), its rows of the device tables, and blocks
+// [blk_lo, blk_lo + nb * ngroups) of the stick kernels (group fastest).
+constexpr int kMaxSeg = 8;
+struct Seg {
+    const void *in;   // stick forward input: c of the segment's first band
+    void *out;        // stick backward output: out of the segment's first band
+    long long s_off;  // element offset of the segment's stick buffer in S
+    int nst, npw, ngroups;
+    int slot_off, group_off, col_off; // first row in slot_info, groups, cols
+    int band_lo, nb, blk_lo;
+};
+struct Launch {
+    int nseg;  // segments in use (1 .. kMaxSeg)
+    int nbt;   // bands of all segments
+    int nblk;  // stick-kernel blocks of all segments
+    Seg seg[kMaxSeg];
+};
+
+// K1: stick z-transforms (G -> r direction) from each segment's c into the
+// stick buffer S.
 template <typename T>
-hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const void *c, int64_t band0,
-                            int nb, void *S, int threads, hipStream_t st);
-// K2: plane kernel.  APPLY: S -> S in place.  G2R: S -> psi rows.  R2G: psi -> S.
+hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                            int threads, hipStream_t st);
+// K2: plane kernel over the planes of every segment.  APPLY: S -> S in place.
+// G2R: S -> psi rows; R2G: psi -> S; DENSITY: weighted |psi|^2 into the
+// partial planes.  The last three take one segment; psi and the weights are
+// indexed from band band0 (the launch's first band in the caller's arrays).
 template <typename T>
-hipError_t launch_plane(const Geometry &g, const DevTables &t, int mode, void *S, const void *V,
-                        void *psi, int64_t band0, int nb, int threads, int lds_bytes,
+hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, int mode, void *S,
+                        const void *V, void *psi, int64_t band0, int threads, int lds_bytes,
                         hipStream_t st);
 // Density helpers (reduce.hip): FP64 reductions and band scaling.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
@@ -59,9 +82,10 @@ template <typename T>
 hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const double *w,
                               const double *scale, double factor, void *y, hipStream_t st);
 
-// K3: stick z-transforms (r -> G direction) with 1/N, gathering into out.
+// K3: stick z-transforms (r -> G direction) with 1/N, gathering into each
+// segment's out.
 template <typename T>
-hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const void *S, void *out,
-                            int64_t band0, int nb, int threads, hipStream_t st);
+hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch &L, const void *S,
+                            int threads, hipStream_t st);
 
 } // namespace vloc

@@ -111,7 +111,8 @@ static bool reciprocal_rows(const double A[9], double B[9])
 }
 
 vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cell[9], double ecut,
-                            const double k[3], const vloc_options *opt, std::string &err)
+                            const double k[3], const vloc_options *opt, std::string &err,
+                            const Occupied *cover)
 {
     if (!grid || !cell || !k) {
         err = "NULL grid, cell or k";
@@ -225,6 +226,16 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         lmin = std::min(lmin, s.lmin);
         lmax = std::max(lmax, s.lmin + s.count - 1);
     }
+    if (cover) {
+        p.hmin = std::min(p.hmin, cover->hmin);
+        p.hmax = std::max(p.hmax, cover->hmax);
+        p.kmin = std::min(p.kmin, cover->kmin);
+        p.kmax = std::max(p.kmax, cover->kmax);
+        lmin = std::min(lmin, cover->lmin);
+        lmax = std::max(lmax, cover->lmax);
+    }
+    p.lmin = lmin;
+    p.lmax = lmax;
     if (p.hmax - p.hmin >= grid[0] || p.kmax - p.kmin >= grid[1] || lmax - lmin >= grid[2]) {
         char buf[160];
         std::snprintf(buf, sizeof buf,
@@ -402,6 +413,8 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     int64_t per_band = (int64_t)Lz * nst * es;
     int64_t chunk = std::max<int64_t>(1, (128LL << 20) / per_band);
     if (p.opt.band_chunk) chunk = p.opt.band_chunk;
+    // stick-kernel blocks of one launch (chunk * ngroups) stay below 2^31
+    chunk = std::min<int64_t>(chunk, INT32_MAX / std::max<int32_t>(1, p.ngroups));
     p.band_chunk = (int32_t)std::min<int64_t>(chunk, 1 << 20);
     return VLOC_OK;
 }

@@ -18,6 +18,12 @@ struct Split {
     int L = 0, L1 = 0, L2 = 0;
 };
 
+// Occupied index ranges a plan must cover at least: the k-points of a batch
+// share one plane layout, so each member covers the union of their ranges.
+struct Occupied {
+    int32_t hmin, hmax, kmin, kmax, lmin, lmax;
+};
+
 struct HostPlan {
     int32_t grid[3] = {0, 0, 0};
     double cell[9] = {};
@@ -28,6 +34,7 @@ struct HostPlan {
     std::vector<int32_t> hkl;      // npw * 3, canonical order
     std::vector<Stick> sticks;     // canonical (h, k) order
     int32_t hmin = 0, hmax = 0, kmin = 0, kmax = 0, nxo = 0;
+    int32_t lmin = 0, lmax = 0;
     int32_t zx = 0, zy = 0, zz = 0; // stage-A input groups that are zero on every line
 
     // deal of sticks to groups; slots are numbered so that each group's
@@ -55,8 +62,10 @@ struct HostPlan {
 };
 
 // Builds everything host-side; returns VLOC_OK or an error with a message.
+// With cover != NULL the occupied ranges are widened to include *cover.
 vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cell[9], double ecut,
-                            const double k[3], const vloc_options *opt, std::string &err);
+                            const double k[3], const vloc_options *opt, std::string &err,
+                            const Occupied *cover = nullptr);
 
 bool split_length(int L, Split &s);
 

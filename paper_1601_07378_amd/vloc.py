@@ -34,6 +34,9 @@ EXPORTS = [
     "vloc_plan_balance", "vloc_plan_stick_groups", "vloc_plan_layout", "vloc_g2r", "vloc_r2g",
     "vloc_status_string", "vloc_last_error", "vloc_plan_enable_timing", "vloc_plan_read_timing",
     "vloc_band_dot", "vloc_weighted_sum", "vloc_density", "vloc_scale_bands",
+    "vloc_batch_create", "vloc_batch_destroy", "vloc_batch_plan", "vloc_batch_set_stream",
+    "vloc_batch_apply", "vloc_batch_use_graph", "vloc_batch_enable_timing",
+    "vloc_batch_read_timing", "vloc_batch_info",
 ]
 
 
@@ -88,6 +91,16 @@ def lib():
         "vloc_weighted_sum": [vp, vp, vp, i64, vp],
         "vloc_density": [vp, vp, i64, vp, vp, vp],
         "vloc_scale_bands": [vp, vp, i64, vp, vp, ctypes.c_double, vp],
+        "vloc_batch_create": [ctypes.POINTER(vp), i32p, dp, ctypes.c_double, ctypes.c_int32, dp,
+                              ctypes.POINTER(Options)],
+        "vloc_batch_destroy": [vp],
+        "vloc_batch_plan": [vp, ctypes.c_int32, ctypes.POINTER(vp)],
+        "vloc_batch_set_stream": [vp, vp],
+        "vloc_batch_apply": [vp, ctypes.POINTER(vp), i64p, vp, ctypes.POINTER(vp)],
+        "vloc_batch_use_graph": [vp, ctypes.c_int32],
+        "vloc_batch_enable_timing": [vp, ctypes.c_int32],
+        "vloc_batch_read_timing": [vp, ctypes.POINTER(ctypes.c_double), i64p],
+        "vloc_batch_info": [vp, i64p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -115,35 +128,51 @@ def _f64(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def make_options(precision: str = "f64", deal: str = "greedy", sticks_per_group: int = 0,
+                 band_chunk: int = 0, plane_rows: int = 0, plane_threads: int = 0,
+                 plane_xwaves: int = 0, plane_xmode: int = 0) -> Options:
+    if precision not in ("f64", "f32"):
+        raise ValueError("precision must be 'f64' or 'f32'")
+    return Options(VLOC_F64 if precision == "f64" else VLOC_F32, DEALS[deal], sticks_per_group,
+                   band_chunk, plane_rows, plane_threads, plane_xwaves, plane_xmode)
+
+
 class Plan:
     """A V_loc plan: grid (N1, N2, N3), cell rows a1..a3, E_cut (Hartree), k in
     reduced coordinates; precision 'f64' or 'f32'."""
 
     def __init__(self, grid, cell, ecut: float, k=(0.0, 0.0, 0.0), precision: str = "f64",
-                 deal: str = "greedy", sticks_per_group: int = 0, band_chunk: int = 0,
-                 plane_rows: int = 0, plane_threads: int = 0, plane_xwaves: int = 0,
-                 plane_xmode: int = 0):
+                 **options):
         self._h = ctypes.c_void_p()
+        self._owner = None
         g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32).reshape(3))
         c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
         kk = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(3))
-        if precision not in ("f64", "f32"):
-            raise ValueError("precision must be 'f64' or 'f32'")
-        opt = Options(VLOC_F64 if precision == "f64" else VLOC_F32, DEALS[deal],
-                      sticks_per_group, band_chunk, plane_rows, plane_threads, plane_xwaves,
-                      plane_xmode)
+        opt = make_options(precision, **options)
         check(lib().vloc_plan_create_ex(ctypes.byref(self._h), _i32(g), _f64(c), float(ecut),
                                         _f64(kk), ctypes.byref(opt)))
+        self._init_sizes(g, precision)
+
+    def _init_sizes(self, g, precision):
         self.grid = tuple(int(x) for x in g)
         self.precision = precision
         n = ctypes.c_int64()
         check(lib().vloc_plan_npw(self._h, ctypes.byref(n)))
         self.npw = int(n.value)
 
+    @classmethod
+    def _borrowed(cls, handle, grid, precision, owner):
+        """Member plan of a batch: valid while the batch lives, never destroyed."""
+        self = cls.__new__(cls)
+        self._h = handle
+        self._owner = owner
+        self._init_sizes(grid, precision)
+        return self
+
     def close(self):
-        if self._h:
+        if self._h and self._owner is None:
             lib().vloc_plan_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -321,3 +350,88 @@ class Plan:
         check(lib().vloc_r2g(self._h, ctypes.c_void_p(psi.data_ptr()), psi.shape[0],
                              ctypes.c_void_p(out.data_ptr())))
         return out
+
+
+class Batch:
+    """Several k-points of one crystal (same grid, cell, E_cut and options)
+    applied with one launch per kernel per band chunk; members share one
+    plane layout.  `kpts` is a sequence of reduced k-vectors (at most 8)."""
+
+    def __init__(self, grid, cell, ecut: float, kpts, precision: str = "f64", **options):
+        self._h = ctypes.c_void_p()
+        g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32).reshape(3))
+        c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+        kk = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64).reshape(-1, 3))
+        opt = make_options(precision, **options)
+        check(lib().vloc_batch_create(ctypes.byref(self._h), _i32(g), _f64(c), float(ecut),
+                                      kk.shape[0], _f64(kk), ctypes.byref(opt)))
+        self.grid = tuple(int(x) for x in g)
+        self.precision = precision
+        self.nk = kk.shape[0]
+        self.plans = []
+        for i in range(self.nk):
+            h = ctypes.c_void_p()
+            check(lib().vloc_batch_plan(self._h, i, ctypes.byref(h)))
+            self.plans.append(Plan._borrowed(h, g, precision, self))
+
+    def close(self):
+        if self._h:
+            for p in self.plans:
+                p._h = ctypes.c_void_p()
+            lib().vloc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        v = np.empty(4, dtype=np.int64)
+        check(lib().vloc_batch_info(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return dict(nk=int(v[0]), band_chunk=int(v[1]), graphs_captured=int(v[2]),
+                    graph_launches=int(v[3]))
+
+    def set_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib().vloc_batch_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def use_graph(self, on: bool = True):
+        check(lib().vloc_batch_use_graph(self._h, 1 if on else 0))
+
+    def enable_timing(self, on: bool = True):
+        check(lib().vloc_batch_enable_timing(self._h, 1 if on else 0))
+
+    def read_timing(self):
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        check(lib().vloc_batch_read_timing(self._h, ms, n))
+        return list(ms), list(n)
+
+    def apply(self, cs, V, outs=None, stream=None):
+        """outs[i] = V_loc cs[i] for each k-point i; cs[i] (nb_i, npw_i) complex
+        device tensors (nb_i may be 0), V (N3, N2, N1) real."""
+        import torch
+        if len(cs) != self.nk:
+            raise ValueError(f"expected {self.nk} coefficient tensors")
+        ct, rt = self.plans[0]._dtypes()
+        if V.dtype != rt or not V.is_cuda or not V.is_contiguous() or \
+                V.numel() != self.grid[0] * self.grid[1] * self.grid[2]:
+            raise ValueError("V must be a contiguous device tensor of N3*N2*N1 values")
+        if outs is None:
+            outs = [torch.empty_like(c) for c in cs]
+        for p, c, o in zip(self.plans, cs, outs):
+            for t in (c, o):
+                if t.dtype != ct or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 \
+                        or t.shape[1] != p.npw:
+                    raise ValueError("each c / out must be a contiguous device tensor (nb, npw)")
+            if o.shape[0] != c.shape[0]:
+                raise ValueError("out and c band counts differ")
+        cp = (ctypes.c_void_p * self.nk)(*[c.data_ptr() for c in cs])
+        op = (ctypes.c_void_p * self.nk)(*[o.data_ptr() for o in outs])
+        nb = (ctypes.c_int64 * self.nk)(*[c.shape[0] for c in cs])
+        self.set_stream(stream)
+        check(lib().vloc_batch_apply(self._h, cp, nb, ctypes.c_void_p(V.data_ptr()), op))
+        return outs

@@ -73,3 +73,12 @@ WORKLOADS = {
     "c5_128": dict(grid=(128, 128, 128), R=32.0, nbands=512, ngauss=32),
     "m0_80": dict(grid=(80, 80, 80), R=float(np.sqrt(413.0)), nbands=1001, ngauss=32),
 }
+
+# Several k-points on one orthorhombic grid: spheres of radius 0.25 min(grid)
+# shifted by k (uneven plane-wave counts) with uneven band counts.
+BATCH_WORKLOADS = {
+    "c4_kpts": dict(grid=(72, 96, 128), R=18.0,
+                    kpts=((0.0, 0.0, 0.0), (0.25, 0.0, 0.0), (0.25, 0.25, 0.0),
+                          (0.25, 0.25, 0.25)),
+                    nbands=(64, 128, 256, 512), ngauss=32),
+}

@@ -1,0 +1,169 @@
+"""GPU checks of batches: several k-points with uneven spheres and band
+counts in one launch per kernel (and per band chunk), eager and replayed from
+a HIP graph.
+
+* every member's output against the CPU oracle (FP64 <= 1e-12 per band; FP32
+  against the oracle on the FP32-rounded inputs, <= 2e-6);
+* the batch equals each member plan's own apply bit for bit (the kernels do
+  the same arithmetic per plane and per stick whatever the work list), also
+  when chunks cut through k-points;
+* graph replays equal the eager result on every replay, with eager work in
+  between, and a change of pointers captures a new graph."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import relerr_per_band
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+vloc = pytest.importorskip("paper_1601_07378_amd.vloc")
+
+C4 = synth.BATCH_WORKLOADS["c4_kpts"]
+CELL = synth.cubic_cell()
+ECUT = synth.ecut_for_radius(C4["R"])
+SKEW = np.array([[6.0, 0.3, -0.2], [0.5, 7.0, 0.4], [-0.3, 0.6, 6.5]])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(require_gpu):
+    yield
+
+
+def label(**kw):
+    print("CASE", kw, flush=True)
+
+
+def dtypes(precision):
+    return (torch.complex128, torch.float64) if precision == "f64" else \
+        (torch.complex64, torch.float32)
+
+
+def inputs(batch, nbands, ngauss, kpts):
+    cs = [synth.coefficients(p.gvectors(), nb, k, ik=i)
+          for i, (p, nb, k) in enumerate(zip(batch.plans, nbands, kpts))]
+    V = synth.potential(batch.grid, ngauss)
+    return cs, V
+
+
+def to_dev(cs, V, precision):
+    ct, rt = dtypes(precision)
+    return ([torch.from_numpy(np.ascontiguousarray(c)).to("cuda", ct) for c in cs],
+            torch.from_numpy(V).to("cuda", rt))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c4_small_bands_vs_oracle(precision):
+    nbands = (3, 0, 5, 2)
+    label(test="batch_vs_oracle", precision=precision, nbands=nbands)
+    b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision=precision)
+    cs, V = inputs(b, nbands, C4["ngauss"], C4["kpts"])
+    dc, dV = to_dev(cs, V, precision)
+    outs = b.apply(dc, dV)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == "f64" else 2e-6
+    for i, (c, o, k) in enumerate(zip(cs, outs, C4["kpts"])):
+        if c.shape[0] == 0:
+            assert o.shape[0] == 0
+            continue
+        ci, Vi = c, V
+        if precision == "f32":
+            ci = c.astype(np.complex64).astype(np.complex128)
+            Vi = V.astype(np.float32).astype(np.float64)
+        ref = oracle.apply(C4["grid"], CELL, ECUT, k, ci, Vi)
+        err = relerr_per_band(o.cpu().numpy().astype(np.complex128), ref)
+        print(precision, "k", k, "max per-band err", err.max())
+        assert err.max() <= tol
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_equals_member_plans_bitwise(precision):
+    nbands = (7, 12, 5, 9)
+    label(test="batch_vs_members", precision=precision)
+    res = {}
+    for chunk in (0, 10, 1):
+        b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision=precision, band_chunk=chunk)
+        cs, V = inputs(b, nbands, C4["ngauss"], C4["kpts"])
+        dc, dV = to_dev(cs, V, precision)
+        outs = b.apply(dc, dV)
+        solo = [p.apply(c, dV) for p, c in zip(b.plans, dc)]
+        torch.cuda.synchronize()
+        for o, s in zip(outs, solo):
+            assert torch.equal(o, s), chunk
+        res[chunk] = [o.cpu() for o in outs]
+    for chunk in (10, 1):
+        for a, c in zip(res[0], res[chunk]):
+            assert torch.equal(a, c), chunk
+
+
+def test_skew_cell_generic_kernels_vs_oracle():
+    """A triclinic cell and a grid with no specialised kernels, three k-points."""
+    grid, ecut = (16, 18, 20), 12.0
+    kpts = ((0.25, 1 / 3, 0.0), (0.0, 0.0, 0.0), (-0.5, 0.1, 0.3))
+    nbands = (2, 3, 1)
+    label(test="batch_skew", grid=grid)
+    b = vloc.Batch(grid, SKEW, ecut, kpts)
+    cs, V = inputs(b, nbands, 4, kpts)
+    dc, dV = to_dev(cs, V, "f64")
+    outs = b.apply(dc, dV)
+    torch.cuda.synchronize()
+    for c, o, k in zip(cs, outs, kpts):
+        ref = oracle.apply(grid, SKEW, ecut, k, c, V)
+        assert relerr_per_band(o.cpu().numpy(), ref).max() <= 1e-12
+
+
+def test_graph_replays_match_eager():
+    nbands = (4, 8, 16, 32)
+    label(test="batch_graph", nbands=nbands)
+    b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision="f32")
+    cs, V = inputs(b, nbands, C4["ngauss"], C4["kpts"])
+    dc, dV = to_dev(cs, V, "f32")
+    eager = [o.clone() for o in b.apply(dc, dV)]
+    torch.cuda.synchronize()
+    b.use_graph(True)
+    outs = [torch.empty_like(c) for c in dc]
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))         # eager work between replays
+        b.apply(dc, dV, outs=outs)
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+        _ = sum(float(c.abs().sum()) for c in dc)  # more eager work, synchronising
+    info = b.info()
+    assert info["graphs_captured"] == 1 and info["graph_launches"] == 4
+    # new output tensors: a second capture, still equal
+    outs2 = b.apply(dc, dV)
+    torch.cuda.synchronize()
+    for o, e in zip(outs2, eager):
+        assert torch.equal(o, e)
+    assert b.info()["graphs_captured"] == 2
+    b.use_graph(False)
+    outs3 = b.apply(dc, dV)
+    torch.cuda.synchronize()
+    for o, e in zip(outs3, eager):
+        assert torch.equal(o, e)
+
+
+def test_c4_full_f32_sampled_vs_oracle():
+    """The full uneven workload (64/128/256/512 bands, FP32, one launch per
+    kernel, graph replay); two bands per k-point against the oracle."""
+    label(test="c4_full")
+    b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision="f32")
+    cs, V = inputs(b, C4["nbands"], C4["ngauss"], C4["kpts"])
+    dc, dV = to_dev(cs, V, "f32")
+    b.use_graph(True)
+    b.apply(dc, dV)                       # capture + first replay
+    outs = b.apply(dc, dV)                # new outs: capture again
+    outs2 = b.apply(dc, dV, outs=outs)    # replay
+    torch.cuda.synchronize()
+    V32 = V.astype(np.float32).astype(np.float64)
+    for i, (c, o, k, nb) in enumerate(zip(cs, outs2, C4["kpts"], C4["nbands"])):
+        sample = [0, nb - 1]
+        ci = c[sample].astype(np.complex64).astype(np.complex128)
+        ref = oracle.apply(C4["grid"], CELL, ECUT, k, ci, V32)
+        err = relerr_per_band(o[sample].cpu().numpy().astype(np.complex128), ref)
+        print("c4 k", k, "f32 err", err.max())
+        assert err.max() <= 2e-6

@@ -115,6 +115,86 @@ def measure(precision, steps, warmup, chunk=0, timing=True):
                 sizes=sizes, layout=lay, balance=bal, out=out, c=c, V=V)
 
 
+SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
+
+
+def measure_batch(steps, warmup):
+    """Several k-points with uneven spheres and band counts (72x96x128, R = 18,
+    4 k-points, 64/128/256/512 bands): FP32 batch replayed from a HIP graph with
+    the tuned schedule, against the plain FP64 path (one plan per k-point, one
+    apply after another) and the FP64 batch."""
+    import torch
+
+    import synth
+    from paper_1601_07378_amd import autotune, vloc
+
+    w = synth.BATCH_WORKLOADS["c4_kpts"]
+    grid, cell, ecut = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"])
+    kpts, nbs = w["kpts"], w["nbands"]
+    total = sum(nbs)
+    tuned, source = {}, "planner default"
+    key = autotune._cache_key(grid, cell, ecut, kpts, nbs, "f32")
+    if os.path.exists(SCHEDULES):
+        with open(SCHEDULES) as f:
+            entry = json.load(f).get(key)
+        if entry:
+            tuned, source = entry["best"], "autotuned (paper_1601_07378_amd/schedules.json)"
+    res = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(run):
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for prec, opts, graph, name in (("f32", autotune.to_options(tuned) if tuned else {}, True,
+                                     "f32_batch_graph"),
+                                    ("f64", {}, False, "f64_batch"),
+                                    ("f64", {}, False, "f64_plain")):
+        ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
+            (torch.complex64, torch.float32)
+        b = vloc.Batch(grid, cell, ecut, kpts, precision=prec, **opts)
+        cs = [torch.from_numpy(synth.coefficients(p.gvectors(), nb, k, ik=i)).to("cuda", ct)
+              for i, (p, nb, k) in enumerate(zip(b.plans, nbs, kpts))]
+        outs = [torch.empty_like(c) for c in cs]
+        V = torch.from_numpy(synth.potential(grid, w["ngauss"])).to("cuda", rt)
+        if name == "f64_plain":
+            plans = [vloc.Plan(grid, cell, ecut, k, precision=prec) for k in kpts]
+            for p in plans:
+                p.set_stream(stream)
+
+            def run():
+                for p, c, o in zip(plans, cs, outs):
+                    p.apply(c, V, out=o, stream=stream)
+        else:
+            b.set_stream(stream)
+            if graph:
+                b.use_graph(True)
+
+            def run():
+                b.apply(cs, V, outs=outs, stream=stream)
+        ms = timed(run)
+        res[name] = {"value": round(total / (ms / 1e3), 1), "ms_per_apply": round(ms, 4)}
+        del b, cs, outs, V
+        torch.cuda.empty_cache()
+    res["speedup_f32_graph_vs_f64_plain"] = round(res["f32_batch_graph"]["value"] /
+                                                  res["f64_plain"]["value"], 3)
+    res["unit"] = "bands/s"
+    res["workload"] = ("72x96x128 grid, |g+k| <= 18, k = (0,0,0), (1/4,0,0), (1/4,1/4,0), "
+                       "(1/4,1/4,1/4) with 64/128/256/512 bands (960 per apply)")
+    res["schedule"] = tuned or "planner default"
+    res["schedule_source"] = source
+    return res
+
+
 def cpu_baseline(nbands_sample: int):
     import oracle
     import synth
@@ -143,6 +223,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of 256 MiB so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -229,6 +310,12 @@ def main():
                          "hbm_frac_path": round(r32["sizes"]["b_alg"] * v32 / HBM_PEAK, 4)}
         log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64)")
         del r32
+    if not args.no_batch and args.precision == "f64":
+        rb = measure_batch(args.steps, args.warmup)
+        result["batched_kpoints"] = rb
+        log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} bands/s, f64 batch "
+            f"{rb['f64_batch']['value']:,.0f}, f64 plain {rb['f64_plain']['value']:,.0f} "
+            f"({rb['schedule_source']})")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(args.cpu_sample)
         result["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()}

@@ -906,10 +906,13 @@ static hipError_t allow_lds(K kernel, size_t bytes)
 }
 
 // Line splits and zero masks compiled as specialisations of the stick
-// kernels; any other plan runs the same kernels with runtime sizes.
+// kernels; any other plan runs the same kernels with runtime sizes.  A
+// specialisation serves every plan whose zero mask contains its own (it then
+// skips fewer of the zero groups), so for each split the larger masks come
+// first.
 #define VLOC_STICK_SPECS(X)                                                                       \
-    X(8, 12, 0x38) X(8, 12, 0) X(4, 6, 0x4) X(4, 6, 0) X(8, 16, 0x38) X(8, 16, 0)               \
-    X(8, 10, 0x38) X(8, 10, 0) X(8, 16, 0x3C)
+    X(8, 12, 0x38) X(8, 12, 0) X(4, 6, 0x4) X(4, 6, 0) X(8, 16, 0x3C) X(8, 16, 0x38)            \
+    X(8, 16, 0) X(8, 10, 0x38) X(8, 10, 0)
 
 template <typename T>
 hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch &L, void *S,
@@ -925,7 +928,7 @@ hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch 
         return hipGetLastError();
     };
 #define VLOC_K1(A, B, Z)                                                                           \
-    if (g.L1z == A && g.L2z == B && g.zz == Z) return go(k_stick_fwd<T, A, B, Z>);
+    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z) return go(k_stick_fwd<T, A, B, Z>);
     VLOC_STICK_SPECS(VLOC_K1)
 #undef VLOC_K1
     return go(k_stick_fwd<T, 0, 0, 0>);
@@ -945,7 +948,7 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch 
         return hipGetLastError();
     };
 #define VLOC_K3(A, B, Z)                                                                           \
-    if (g.L1z == A && g.L2z == B && g.zz == Z) return go(k_stick_bwd<T, A, B, Z>);
+    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z) return go(k_stick_bwd<T, A, B, Z>);
     VLOC_STICK_SPECS(VLOC_K3)
 #undef VLOC_K3
     return go(k_stick_bwd<T, 0, 0, 0>);
@@ -999,7 +1002,8 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const
         return hipErrorInvalidValue;
     }
 #define VLOC_PLANE_CASE(X1, X2, Y1, Y2, ZX, ZY)                                                    \
-    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && g.zx == ZX && g.zy == ZY)     \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
+        (g.zy & ZY) == ZY)                                                                        \
         return launch_plane_sized<T, MODE, X1, X2, Y1, Y2, ZX, ZY>(g, t, L, S, V, psi, band0,     \
                                                                    threads, lds, st);
     VLOC_PLANE_CASE(8, 12, 8, 12, 0x38, 0x38)
@@ -1010,8 +1014,8 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const
     VLOC_PLANE_CASE(8, 16, 8, 16, 0, 0)
     VLOC_PLANE_CASE(8, 10, 8, 10, 0x38, 0x38)
     VLOC_PLANE_CASE(8, 10, 8, 10, 0, 0)
-    VLOC_PLANE_CASE(8, 9, 8, 12, 0, 0)
     VLOC_PLANE_CASE(8, 9, 8, 12, 0x38, 0x3C)
+    VLOC_PLANE_CASE(8, 9, 8, 12, 0, 0)
 #undef VLOC_PLANE_CASE
     return launch_plane_sized<T, MODE, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads, lds,
                                                          st);

@@ -18,16 +18,24 @@ namespace vloc {
 
 static const double kTwoPi = 6.283185307179586476925286766559;
 
+static const int kCodelets[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16};
+
+bool is_codelet(int r)
+{
+    for (int c : kCodelets)
+        if (c == r) return true;
+    return false;
+}
+
 bool split_length(int L, Split &s)
 {
-    static const int codelets[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16};
+    const int *codelets = kCodelets;
     int best1 = 0, best2 = 0;
-    for (int a : codelets) {
+    for (int i = 0; i < 12; ++i) {
+        const int a = codelets[i];
         if (L % a) continue;
         int b = L / a;
-        bool ok = false;
-        for (int c : codelets) ok |= (c == b);
-        if (!ok || a > b) continue;
+        if (!is_codelet(b) || a > b) continue;
         if (best1 == 0 || (b - a) < (best2 - best1)) {
             best1 = a;
             best2 = b;
@@ -148,6 +156,21 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         !split_length(grid[2], p.sz)) {
         err = "grid dimension is not a product of two codelet sizes {1..6,8,9,10,12,15,16}";
         return VLOC_E_GRID;
+    }
+    {
+        Split *sp[3] = {&p.sx, &p.sy, &p.sz};
+        for (int a = 0; a < 3; ++a) {
+            const int l1 = p.opt.split[a];
+            if (!l1) continue;
+            const int L = grid[a];
+            if (l1 < 0 || L % l1 || !is_codelet(l1) || !is_codelet(L / l1)) {
+                err = "split[" + std::to_string(a) + "] = " + std::to_string(l1) +
+                      " does not split " + std::to_string(L) + " into two codelet lengths";
+                return VLOC_E_INVALID;
+            }
+            sp[a]->L1 = l1;
+            sp[a]->L2 = L / l1;
+        }
     }
     for (int i = 0; i < 9; ++i) {
         p.cell[i] = cell[i];

@@ -68,6 +68,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
                             const Occupied *cover = nullptr);
 
 bool split_length(int L, Split &s);
+bool is_codelet(int r); // r is a compiled codelet length
 
 // exp(-2 pi i j / L) for j < L, FP64, angle numerator reduced exactly.
 std::vector<double> twiddle_table(int L);

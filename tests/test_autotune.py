@@ -1,0 +1,87 @@
+"""Autotuner: its search space (CPU) and one tuning run whose pick is then
+checked against the oracle (GPU)."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+vloc = pytest.importorskip("paper_1601_07378_amd.vloc")
+at = pytest.importorskip("paper_1601_07378_amd.autotune")
+
+C4 = synth.BATCH_WORKLOADS["c4_kpts"]
+
+
+def test_axis_splits():
+    assert at.axis_splits(96) == [6, 8, 12, 16]
+    assert at.axis_splits(72) == [6, 8, 9, 12]
+    assert at.axis_splits(128) == [8, 16]
+    assert at.axis_splits(7) == []
+    assert at.axis_splits(5) == [1, 5]
+    for L in (24, 80, 96, 100, 128, 144):
+        for a in at.axis_splits(L):
+            assert L % a == 0 and (L // a) in at.CODELETS
+
+
+def test_every_single_knob_candidate_plans():
+    """Each one-knob departure from the defaults is accepted by the planner
+    (host work only), and the split knobs reach the plan's layout."""
+    grid, cell, ecut = C4["grid"], synth.cubic_cell(), synth.ecut_for_radius(C4["R"])
+    space = at.knob_space(grid, "f32", True, sum(C4["nbands"]))
+    base = {k: v[0] for k, v in space.items()}
+    for knob, values in space.items():
+        for v in values:
+            cfg = dict(base)
+            cfg[knob] = v
+            b = vloc.Batch(grid, cell, ecut, C4["kpts"], precision="f32", **at.to_options(cfg))
+            lay = b.plans[0].layout()
+            if knob == "split_x" and v:
+                assert (lay["L1x"], lay["L2x"]) == (v, grid[0] // v)
+            if knob == "split_z" and v:
+                assert (lay["L1z"], lay["L2z"]) == (v, grid[2] // v)
+            if knob == "plane_xmode" and v:
+                assert lay["plane_xmode"] == 2
+            b.close()
+
+
+def test_split_option_validation():
+    cell = synth.cubic_cell()
+    p = vloc.Plan((96, 96, 96), cell, 288.0, split=(12, 6, 16))
+    lay = p.layout()
+    assert (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"], lay["L1z"], lay["L2z"]) == \
+        (12, 8, 6, 16, 16, 6)
+    for bad in ((7, 0, 0), (0, 5, 0), (0, 0, 32), (-2, 0, 0)):
+        with pytest.raises(vloc.VlocError) as e:
+            vloc.Plan((96, 96, 96), cell, 288.0, split=bad)
+        assert e.value.status == vloc.VLOC_E_INVALID
+    # the stick map does not depend on the schedule
+    assert np.array_equal(p.gvectors(), vloc.Plan((96, 96, 96), cell, 288.0).gvectors())
+
+
+@pytest.mark.gpu
+def test_tuner_pick_is_correct(require_gpu, tmp_path):
+    import torch
+    grid, cell, ecut = (24, 24, 24), synth.cubic_cell(), 18.0
+    kpts = [(0, 0, 0), (0.25, 0.25, 0)]
+    nb = [6, 9]
+    print("CASE tuner", grid, flush=True)
+    cache = str(tmp_path / "tune.json")
+    best = at.tune_cached(cache, grid, cell, ecut, kpts, nb, precision="f64", reps=3)
+    data = json.load(open(cache))
+    (entry,) = data.values()
+    assert entry["best"] == best and entry["trials"] > 5
+    assert entry["best_ms"] > 0 and entry["default_ms"] > 0
+    assert at.tune_cached(cache, grid, cell, ecut, kpts, nb, precision="f64") == best
+    b = vloc.Batch(grid, cell, ecut, kpts, precision="f64", **at.to_options(best))
+    b.use_graph(True)
+    cs = [synth.coefficients(p.gvectors(), n, k, ik=i)
+          for i, (p, n, k) in enumerate(zip(b.plans, nb, kpts))]
+    V = synth.potential(grid, 4)
+    outs = b.apply([torch.from_numpy(c).cuda() for c in cs], torch.from_numpy(V).cuda())
+    torch.cuda.synchronize()
+    for c, o, k in zip(cs, outs, kpts):
+        ref = oracle.apply(grid, cell, ecut, k, c, V)
+        err = np.linalg.norm(o.cpu().numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        assert err.max() <= 1e-12

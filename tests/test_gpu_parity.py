@@ -222,3 +222,25 @@ def test_plane_xmodes_vs_oracle(xmode, precision, name, grid, cell, ecut, k, nb)
     err = relerr_per_band(got, ref)
     print(name, precision, "xmode", xmode, "err", err.max())
     assert err.max() <= tol
+
+
+# ------------------------------------------- radix splits chosen by option
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("split", [(12, 6, 16), (16, 16, 6), (6, 12, 8)])
+def test_radix_splits_vs_oracle(split, precision):
+    """Non-default L = L1 * L2 splits (run-time sized kernels) on 96^3."""
+    grid, cell, ecut, k, nb = (96, 96, 96), synth.cubic_cell(), 288.0, (0, 0, 0), 2
+    label(test="split", split=split, precision=precision)
+    hkl, c, V = case(grid, cell, ecut, k, nb)
+    p = vloc.Plan(grid, cell, ecut, k, precision=precision, split=split)
+    got = run(p, c, V)
+    if precision == "f64":
+        ref, tol = oracle.apply(grid, cell, ecut, k, c, V), TOL64
+    else:
+        ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                           V.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    err = relerr_per_band(got, ref)
+    print("split", split, precision, "err", err.max())
+    assert err.max() <= tol

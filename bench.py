@@ -74,7 +74,7 @@ def workload_sizes(plan, grid, nbands, precision):
     return dict(nst=nst, npw=npw, nxo=nxo, N=N, s=s, sv=sv, b_alg=b_alg, f_alg=f_alg)
 
 
-def measure(precision, steps, warmup, chunk=0, timing=True):
+def measure(precision, steps, warmup, chunk=0, timing=True, gamma=False):
     import torch
 
     import synth
@@ -82,7 +82,7 @@ def measure(precision, steps, warmup, chunk=0, timing=True):
 
     w = synth.WORKLOADS["c2_96"]
     grid, cell, ecut, nb = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"]), w["nbands"]
-    plan = vloc.Plan(grid, cell, ecut, precision=precision, band_chunk=chunk)
+    plan = vloc.Plan(grid, cell, ecut, precision=precision, band_chunk=chunk, gamma=gamma)
     hkl = plan.gvectors()
     ct, rt = (torch.complex128, torch.float64) if precision == "f64" else (torch.complex64, torch.float32)
     c = torch.from_numpy(synth.coefficients(hkl, nb)).to("cuda", ct)
@@ -224,6 +224,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-gamma", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of 256 MiB so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -310,6 +311,23 @@ def main():
                          "hbm_frac_path": round(r32["sizes"]["b_alg"] * v32 / HBM_PEAK, 4)}
         log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64)")
         del r32
+    if not args.no_gamma and args.precision == "f64":
+        # the paper's real mode (Gamma point, half sphere, two bands per transform)
+        # on the same grid and sphere: a different input class (real psi), so it
+        # is reported beside the complex-path value, not as it
+        gm = {}
+        for prec in ("f64", "f32"):
+            rg = measure(prec, args.steps, args.warmup, args.chunk, timing=False, gamma=True)
+            vg = rg["nb"] * args.steps / (rg["ms_total"] / 1e3)
+            gm[prec] = {"value": round(vg, 1), "ms_per_step": round(rg["ms_total"] / args.steps, 4)}
+            del rg
+        gm["unit"] = "bands/s"
+        gm["speedup_f64_vs_complex_f64"] = round(gm["f64"]["value"] / bands_per_s, 3)
+        gm["workload"] = ("96^3, |G|<=24, 256 real bands (half sphere 28889 coefficients per "
+                          "band), two bands per complex transform")
+        result["gamma_real_mode"] = gm
+        log(f"# gamma real mode: f64 {gm['f64']['value']:,.0f} bands/s, "
+            f"f32 {gm['f32']['value']:,.0f} bands/s")
     if not args.no_batch and args.precision == "f64":
         rb = measure_batch(args.steps, args.warmup)
         result["batched_kpoints"] = rb

@@ -84,6 +84,22 @@ typedef struct {
                                  buffers in LDS, 2 = one lane quad per row (needs
                                  N1 in {24, 72, 80, 96} with the matching y split
                                  and N2 <= 128)                                    */
+    int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
+                                 each axis (x, y, z); 0 = automatic (the most
+                                 balanced split); else L1 and L / L1 must both be
+                                 codelet lengths {1..6, 8, 9, 10, 12, 15, 16}.
+                                 Common grids run kernels compiled for their
+                                 automatic split; other splits run the same
+                                 kernels with run-time sizes                       */
+    int32_t gamma;            /* 1 = real mode (needs k = 0): wave functions are real
+                                 in space, c(-g) = conj(c(g)); c and out hold only
+                                 the half sphere H = {h > 0} u {h = 0, k > 0} u
+                                 {h = k = 0, l >= 0} (canonical order restricted to
+                                 H; vloc_plan_npw / gvectors describe H) and two
+                                 bands share one complex transform (the paper's
+                                 gamma-point variant, Sec. 4.3).  Im c(0) is taken
+                                 as 0 and Im out(0) is 0.  Only vloc_apply accepts
+                                 such plans                                       */
 } vloc_options;
 
 /* Build a plan (host work only; device tables are uploaded on first use).
@@ -116,13 +132,16 @@ vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream);
 vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void *V, void *out);
 
 /* ---------------------------------------------------------------- queries */
-/* Host outputs, caller-allocated. */
+/* Host outputs, caller-allocated.  npw and gvectors describe the
+ * coefficients of one band in the caller's arrays (the half sphere for a
+ * real-mode plan); the stick, balance and group queries always describe the
+ * whole sphere. */
 vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw);
 /* hkl: npw*3 int32 (h, k, l) in canonical order. */
 vloc_status vloc_plan_gvectors(vloc_plan plan, int32_t *hkl);
 /* Stick table in canonical order: nsticks rows of (h, k, offset, count, lmin),
- * where the run c[offset .. offset+count) holds l = lmin .. lmin+count-1.
- * table may be NULL to query the count only. */
+ * where the run [offset .. offset+count) of the whole sphere's canonical order
+ * holds l = lmin .. lmin+count-1.  table may be NULL to query the count only. */
 vloc_status vloc_plan_sticks(vloc_plan plan, int64_t *nsticks, int32_t *table);
 /* Plane waves per stick group after the deal (the load-balance statistic of
  * the paper's Tab. 2, per workgroup instead of per process).  pw_per_group may

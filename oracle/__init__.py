@@ -227,3 +227,42 @@ def group_loads(counts, group, ngroups: int) -> np.ndarray:
     loads = np.zeros(ngroups, dtype=np.int64)
     np.add.at(loads, np.asarray(group), np.asarray(counts, dtype=np.int64))
     return loads
+
+
+# ------------------------------------------------------------ real (gamma) mode
+# Sec. 4.3, last paragraph: at the Gamma point psi_n is real in space, so
+# c_n(-G) = conj(c_n(G)) and half of reciprocal space suffices.  The half
+# sphere kept is H = {h > 0} u {h = 0, k > 0} u {h = k = 0, l >= 0}, in the
+# canonical order restricted to H; Im c(0) is taken as zero.
+
+
+def half_mask(hkl) -> np.ndarray:
+    """True for the points of the full sphere that belong to H."""
+    h, k, l = (np.asarray(hkl)[:, i] for i in range(3))
+    return (h > 0) | ((h == 0) & (k > 0)) | ((h == 0) & (k == 0) & (l >= 0))
+
+
+def expand_half(hkl_full, c_half) -> np.ndarray:
+    """Full-sphere coefficients from half-sphere ones: c(g) on H, conj c(-g)
+    off H, real c(0)."""
+    hkl_full = np.asarray(hkl_full)
+    m = half_mask(hkl_full)
+    c_half = np.atleast_2d(np.asarray(c_half, dtype=np.complex128))
+    full = np.zeros((c_half.shape[0], hkl_full.shape[0]), dtype=np.complex128)
+    full[:, m] = c_half
+    index = {tuple(g): i for i, g in enumerate(hkl_full.tolist())}
+    for i in np.nonzero(~m)[0]:
+        j = index[tuple((-hkl_full[i]).tolist())]
+        full[:, i] = np.conj(full[:, j])
+    z = np.nonzero((hkl_full == 0).all(axis=1))[0]
+    full[:, z] = full[:, z].real
+    return full
+
+
+def apply_gamma(grid, cell, ecut, c_half, V, nthreads: int = 0) -> np.ndarray:
+    """V_loc on half-sphere coefficients: expand, apply the full operator,
+    keep H."""
+    hkl = sphere_py(cell, ecut)
+    full = expand_half(hkl, c_half)
+    out = apply(grid, cell, ecut, (0.0, 0.0, 0.0), full, V, nthreads=nthreads)
+    return out[:, half_mask(hkl)]

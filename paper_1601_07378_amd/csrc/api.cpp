@@ -31,6 +31,7 @@ struct Engine {
     int4 *d_slot = nullptr;
     int2 *d_groups = nullptr;
     int2 *d_cols = nullptr;
+    int4 *d_gam = nullptr;
     void *d_tw[3] = {nullptr, nullptr, nullptr};
     double2 *d_twx64 = nullptr;
     std::vector<int> slot_off, group_off, col_off;
@@ -94,6 +95,7 @@ void free_device(Engine &E)
     free_ptr(E.d_slot);
     free_ptr(E.d_groups);
     free_ptr(E.d_cols);
+    free_ptr(E.d_gam);
     free_ptr(E.d_twx64);
     for (void *&t : E.d_tw) free_ptr(t);
     free_ptr(E.d_S);
@@ -133,7 +135,7 @@ vloc_status upload(Engine &E)
     if ((e = hipGetDevice(&E.device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
 
     // member tables, concatenated: slots and groups relative to the member
-    std::vector<int4> slot;
+    std::vector<int4> slot, gam;
     std::vector<int2> groups, cols;
     E.slot_off.clear();
     E.group_off.clear();
@@ -155,11 +157,29 @@ vloc_status upload(Engine &E)
             groups.push_back(make_int2(m->group_start[g], m->group_size[g]));
             cap = std::max(cap, m->group_size[g]);
         }
+        if (m->gamma) {
+            // per slot: source offset, kind, -lmin of (0, 0), mirror's index in the group
+            std::vector<int32_t> slot_of(m->nst());
+            for (int64_t s = 0; s < m->nst(); ++s) slot_of[m->stick_of_slot[s]] = (int32_t)s;
+            for (int64_t s = 0; s < m->nst(); ++s) {
+                const int32_t i = m->stick_of_slot[s];
+                const Stick &st = m->sticks[i];
+                const int32_t mi = m->mirror[i];
+                const int32_t rel = slot_of[mi] - m->group_start[m->group_of_stick[i]];
+                if (st.h == 0 && st.k == 0)
+                    gam.push_back(make_int4(m->half_off[i], 2, -st.lmin, rel));
+                else if (m->half_off[i] >= 0)
+                    gam.push_back(make_int4(m->half_off[i], 0, 0, rel));
+                else
+                    gam.push_back(make_int4(m->half_off[mi] + st.count - 1, 1, 0, rel));
+            }
+        }
         for (int c = 0; c < m->nxo; ++c) cols.push_back(make_int2(m->col_kmin[c], m->col_kcnt[c]));
     }
     if ((e = upload_vec(E.d_slot, slot)) != hipSuccess) goto devfail;
     if ((e = upload_vec(E.d_groups, groups)) != hipSuccess) goto devfail;
     if ((e = upload_vec(E.d_cols, cols)) != hipSuccess) goto devfail;
+    if (!gam.empty() && (e = upload_vec(E.d_gam, gam)) != hipSuccess) goto devfail;
     {
         const Split *sp[3] = {&h.sx, &h.sy, &h.sz};
         for (int a = 0; a < 3; ++a) {
@@ -217,6 +237,7 @@ vloc_status upload(Engine &E)
         g.resident_plane_wgs = cus * per_cu;
         g.nsub = 1;
         g.group_cap = cap;
+        g.gamma = h.gamma ? 1 : 0;
         g.inv_n = 1.0 / ((double)g.N1 * g.N2 * g.N3);
     }
     E.uploaded = true;
@@ -269,6 +290,7 @@ DevTables tables(const Engine &E)
     t.twx64 = E.d_twx64;
     t.partial = E.d_partial;
     t.wts = nullptr;
+    t.gam = E.d_gam;
     return t;
 }
 
@@ -295,8 +317,8 @@ struct Part {
 
 // The launches of one call: the caller's bands of every member, concatenated
 // in member order, cut into chunks of at most `chunk` bands; a chunk holds one
-// segment per member it touches.  Returns the stick-buffer bytes of the
-// largest chunk.
+// segment per member it touches.  In the real mode a launch band is a pair of
+// the caller's bands.  Returns the stick-buffer bytes of the largest chunk.
 size_t make_launches(const Engine &E, const void *const *in, void *const *out,
                      const int64_t *nbands, int64_t chunk, std::vector<Launch> &ls)
 {
@@ -316,12 +338,16 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
             const Part &p = cur[i];
             const HostPlan &m = *E.members[p.member];
             const size_t es = (size_t)m.elem_bytes();
+            const int64_t per = m.gamma ? 2 : 1; // caller bands per launch band
+            const int64_t first = per * p.b0;    // first caller band of the segment
             Seg &s = L.seg[i];
-            s.in = in ? static_cast<const char *>(in[p.member]) + p.b0 * m.npw() * es : nullptr;
-            s.out = out ? static_cast<char *>(out[p.member]) + p.b0 * m.npw() * es : nullptr;
+            s.in = in ? static_cast<const char *>(in[p.member]) + first * m.npw_io() * es
+                      : nullptr;
+            s.out = out ? static_cast<char *>(out[p.member]) + first * m.npw_io() * es : nullptr;
+            s.nbr = (int)std::min<int64_t>(per * p.nb, nbands[p.member] - first);
             s.s_off = s_off;
             s.nst = (int)m.nst();
-            s.npw = (int)m.npw();
+            s.npw = (int)m.npw_io();
             s.ngroups = m.ngroups;
             s.slot_off = E.slot_off[p.member];
             s.group_off = E.group_off[p.member];
@@ -341,9 +367,10 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
         cur_bands = 0;
     };
     for (int m = 0; m < nm; ++m) {
+        const int64_t units = E.members[m]->gamma ? (nbands[m] + 1) / 2 : nbands[m];
         int64_t b = 0;
-        while (b < nbands[m]) {
-            int64_t take = std::min(nbands[m] - b, chunk - cur_bands);
+        while (b < units) {
+            int64_t take = std::min(units - b, chunk - cur_bands);
             cur.push_back(Part{m, b, (int)take});
             cur_bands += take;
             b += take;
@@ -505,7 +532,7 @@ vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void
     if (!c || !V || !out) return fail(VLOC_E_INVALID, "NULL c, V or out");
     const HostPlan &h = plan->hp;
     size_t es = (size_t)h.elem_bytes();
-    size_t cbytes = (size_t)nbands * (size_t)h.npw() * es;
+    size_t cbytes = (size_t)nbands * (size_t)h.npw_io() * es;
     size_t vbytes = (size_t)h.grid[0] * h.grid[1] * h.grid[2] * (es / 2);
     if (overlaps(out, cbytes, c, cbytes) || overlaps(out, cbytes, V, vbytes))
         return fail(VLOC_E_ALIAS, "out overlaps c or V");
@@ -520,6 +547,7 @@ vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r)
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!c || !psi_r) return fail(VLOC_E_INVALID, "NULL c or psi_r");
+    if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     const HostPlan &h = plan->hp;
     size_t es = (size_t)h.elem_bytes();
     size_t cbytes = (size_t)nbands * (size_t)h.npw() * es;
@@ -534,6 +562,7 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!c_out || !psi_r) return fail(VLOC_E_INVALID, "NULL psi_r or c_out");
+    if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     const HostPlan &h = plan->hp;
     size_t es = (size_t)h.elem_bytes();
     size_t cbytes = (size_t)nbands * (size_t)h.npw() * es;
@@ -561,6 +590,7 @@ vloc_status vloc_band_dot(vloc_plan plan, const void *a, const void *b, int64_t 
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!a || !b || !e) return fail(VLOC_E_INVALID, "NULL a, b or e");
+    if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     vloc_status s = upload(plan->eng);
     if (s != VLOC_OK) return s;
     hipStream_t st = plan->eng.stream;
@@ -589,6 +619,7 @@ vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, cons
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!x || !y) return fail(VLOC_E_INVALID, "NULL x or y");
+    if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     vloc_status s = upload(plan->eng);
     if (s != VLOC_OK) return s;
     const int64_t npw = plan->hp.npw();
@@ -606,6 +637,7 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
     if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
     if (nbands == 0) return VLOC_OK;
     if (!c || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, w or rho");
+    if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     if (plan->hp.plane_xq) return fail(VLOC_E_INVALID, "density needs the row-buffer x pass");
     Engine &E = plan->eng;
     vloc_status s = upload(E);
@@ -659,14 +691,15 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
 vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw)
 {
     if (!plan || !npw) return fail(VLOC_E_INVALID, "NULL argument");
-    *npw = plan->hp.npw();
+    *npw = plan->hp.npw_io();
     return VLOC_OK;
 }
 
 vloc_status vloc_plan_gvectors(vloc_plan plan, int32_t *hkl)
 {
     if (!plan || !hkl) return fail(VLOC_E_INVALID, "NULL argument");
-    std::memcpy(hkl, plan->hp.hkl.data(), plan->hp.hkl.size() * sizeof(int32_t));
+    const std::vector<int32_t> &v = plan->hp.gamma ? plan->hp.half_hkl : plan->hp.hkl;
+    std::memcpy(hkl, v.data(), v.size() * sizeof(int32_t));
     return VLOC_OK;
 }
 
@@ -730,6 +763,7 @@ vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const do
     *batch = nullptr;
     if (nk < 1 || nk > kMaxSeg) return fail(VLOC_E_INVALID, "nk must be in [1, 8]");
     if (!kpts) return fail(VLOC_E_INVALID, "kpts is NULL");
+    if (opt && opt->gamma) return fail(VLOC_E_INVALID, "batches run the complex mode only");
     vloc_batch b = new (std::nothrow) vloc_batch_s();
     if (!b) return fail(VLOC_E_NOMEM, "host allocation failed");
     std::string err;

@@ -135,12 +135,42 @@ __device__ __forceinline__ Seg seg_at(const Launch &L, int s)
     return r;
 }
 
+// Real mode: the value at position i of a stick's run for the band pair
+// (a, b), d = A + i B, where A, B are the coefficients of bands a, b at that
+// g; a mirror stick (-h, -k) reads the half-sphere run of its partner in
+// reverse, conjugated (c(-g) = conj c(g)); the (0, 0) stick reads l >= 0
+// directly and l < 0 mirrored, with Im c(0) taken as 0.
+template <typename T>
+__device__ __forceinline__ cx<T> gamma_pair(const cx<T> *__restrict__ ca,
+                                            const cx<T> *__restrict__ cb, int4 gm, int i)
+{
+    int idx;
+    bool mir, zero = false;
+    if (gm.y == 0) {
+        idx = gm.x + i;
+        mir = false;
+    } else if (gm.y == 1) {
+        idx = gm.x - i;
+        mir = true;
+    } else {
+        const int l = i - gm.z;
+        mir = l < 0;
+        zero = l == 0;
+        idx = gm.x + (mir ? -l : l);
+    }
+    cx<T> a = ca[idx];
+    cx<T> b = cb ? cb[idx] : mk<T>(T(0), T(0));
+    T ai = mir ? -a.y : a.y, bi = mir ? -b.y : b.y;
+    if (zero) ai = bi = T(0);
+    return mk<T>(a.x - bi, ai + b.x);
+}
+
 // ------------------------------------------------------------------ K1
 // One workgroup per (stick group, band) of a segment.  Stage A loads c
 // straight from HBM (only the stick's own run is non-zero), stage B writes the
 // z-transformed stick to S[band][z][slot]; lanes of consecutive sticks write
 // consecutive slots.
-template <typename T, int CZ1, int CZ2, int ZZ>
+template <typename T, int CZ1, int CZ2, int ZZ, bool GAM>
 __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Launch L,
                                                    cx<T> *__restrict__ S)
 {
@@ -152,7 +182,10 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
     const int2 gi = t.groups[sg.group_off + gr];
     const int s0 = gi.x, ns = gi.y;
     const int4 *slot_info = t.slot_info + sg.slot_off;
-    const cx<T> *cb = reinterpret_cast<const cx<T> *>(sg.in) + bl * (long long)sg.npw;
+    // real mode: launch band bl is the pair of real bands 2 bl, 2 bl + 1
+    const cx<T> *cb = reinterpret_cast<const cx<T> *>(sg.in) +
+                      (GAM ? 2 * bl : bl) * (long long)sg.npw;
+    const cx<T> *cb2 = (GAM && 2 * bl + 1 < sg.nbr) ? cb + sg.npw : nullptr;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
     const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
     const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
@@ -162,6 +195,8 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
         for (int task = threadIdx.x; task < ns * L2; task += blockDim.x) {
             const int j = task / L2, n2 = task - j * L2;
             const int4 si = slot_info[s0 + j];
+            int4 gm = make_int4(0, 0, 0, 0);
+            if (GAM) gm = t.gam[sg.slot_off + s0 + j];
             T xr[R], xi[R];
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
@@ -169,7 +204,7 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
                 if (!masked<ZZ>(n1)) {
                     int i = n2 + L2 * n1 - si.z;
                     if (i < 0) i += N3;
-                    if (i < si.y) v = cb[si.x + i];
+                    if (i < si.y) v = GAM ? gamma_pair<T>(cb, cb2, gm, i) : cb[si.x + i];
                 }
                 xr[n1] = v.x;
                 xi[n1] = v.y;
@@ -206,7 +241,7 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
 // ------------------------------------------------------------------ K3
 // Mirror of K1: stage B' reads S[band][z][slot] (coalesced over sticks), stage
 // A' keeps only the stick's own run, scales by 1/N and writes out.
-template <typename T, int CZ1, int CZ2, int ZZ>
+template <typename T, int CZ1, int CZ2, int ZZ, bool GAM>
 __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Launch L,
                                                    const cx<T> *__restrict__ S)
 {
@@ -218,7 +253,7 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
     const int2 gi = t.groups[sg.group_off + gr];
     const int s0 = gi.x, ns = gi.y;
     const int4 *slot_info = t.slot_info + sg.slot_off;
-    cx<T> *ob = reinterpret_cast<cx<T> *>(sg.out) + bl * (long long)sg.npw;
+    cx<T> *ob = reinterpret_cast<cx<T> *>(sg.out) + (GAM ? 2 * bl : bl) * (long long)sg.npw;
     const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
     const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
     const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
@@ -257,16 +292,50 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
             }
             twiddle<R, +1, T>(xr, xi, n2, tw);
             Dft<R, +1, T>::run(xr, xi);
-            const int4 si = slot_info[s0 + j];
+            if constexpr (GAM) {
+                // back into the line in natural z order (the task's own positions)
+                cx<T> *ln = lines + j * ldz + n2;
 #pragma unroll
-            for (int n1 = 0; n1 < R; ++n1) {
-                if (masked<ZZ>(n1)) continue;
-                int i = n2 + L2 * n1 - si.z;
-                if (i < 0) i += N3;
-                if (i < si.y) ob[si.x + i] = mk<T>(xr[n1] * inv_n, xi[n1] * inv_n);
+                for (int n1 = 0; n1 < R; ++n1)
+                    if (!masked<ZZ>(n1)) ln[L2 * n1] = mk<T>(xr[n1], xi[n1]);
+            } else {
+                const int4 si = slot_info[s0 + j];
+#pragma unroll
+                for (int n1 = 0; n1 < R; ++n1) {
+                    if (masked<ZZ>(n1)) continue;
+                    int i = n2 + L2 * n1 - si.z;
+                    if (i < 0) i += N3;
+                    if (i < si.y) ob[si.x + i] = mk<T>(xr[n1] * inv_n, xi[n1] * inv_n);
+                }
             }
         }
     });
+    if constexpr (GAM) {
+        // Split the pair: with e = transform of d = A + i B at g and f at -g,
+        // A(g) = (e + conj f) / 2 and B(g) = (e - conj f) / (2 i); only the
+        // half sphere is written (sticks of H and l >= 0 of the (0, 0) stick).
+        __syncthreads();
+        cx<T> *ob2 = (2 * bl + 1 < sg.nbr) ? ob + sg.npw : nullptr;
+        const T h = T(0.5 * g.inv_n);
+        for (int task = threadIdx.x; task < ns * N3; task += blockDim.x) {
+            const int j = task / N3, z = task - j * N3;
+            const int4 gm = t.gam[sg.slot_off + s0 + j];
+            if (gm.y == 1) continue;
+            const int4 si = slot_info[s0 + j];
+            int i = z - si.z;
+            if (i < 0) i += N3;
+            if (i >= si.y) continue;
+            int oi = gm.x + i;
+            if (gm.y == 2) {
+                if (i < gm.z) continue;
+                oi = gm.x + (i - gm.z);
+            }
+            const cx<T> e = lines[j * ldz + z];
+            const cx<T> f = lines[gm.w * ldz + (z == 0 ? 0 : N3 - z)];
+            ob[oi] = mk<T>((e.x + f.x) * h, (e.y - f.y) * h);
+            if (ob2) ob2[oi] = mk<T>((e.y + f.y) * h, (f.x - e.x) * h);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ K2
@@ -928,10 +997,11 @@ hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch 
         return hipGetLastError();
     };
 #define VLOC_K1(A, B, Z)                                                                           \
-    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z) return go(k_stick_fwd<T, A, B, Z>);
+    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z)                                              \
+        return g.gamma ? go(k_stick_fwd<T, A, B, Z, true>) : go(k_stick_fwd<T, A, B, Z, false>);
     VLOC_STICK_SPECS(VLOC_K1)
 #undef VLOC_K1
-    return go(k_stick_fwd<T, 0, 0, 0>);
+    return g.gamma ? go(k_stick_fwd<T, 0, 0, 0, true>) : go(k_stick_fwd<T, 0, 0, 0, false>);
 }
 
 template <typename T>
@@ -948,10 +1018,11 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch 
         return hipGetLastError();
     };
 #define VLOC_K3(A, B, Z)                                                                           \
-    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z) return go(k_stick_bwd<T, A, B, Z>);
+    if (g.L1z == A && g.L2z == B && (g.zz & Z) == Z)                                              \
+        return g.gamma ? go(k_stick_bwd<T, A, B, Z, true>) : go(k_stick_bwd<T, A, B, Z, false>);
     VLOC_STICK_SPECS(VLOC_K3)
 #undef VLOC_K3
-    return go(k_stick_bwd<T, 0, 0, 0>);
+    return g.gamma ? go(k_stick_bwd<T, 0, 0, 0, true>) : go(k_stick_bwd<T, 0, 0, 0, false>);
 }
 
 template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int ZY>

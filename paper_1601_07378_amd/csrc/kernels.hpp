@@ -16,6 +16,10 @@ struct DevTables {
     const double2 *twx64;        // exp(-2 pi i j / N1) in FP64 (quad x pass)
     double *partial;             // density: [nsub][N3][N2][N1] partial sums (FP64)
     const double *wts;           // density: band weights (FP64)
+    // real mode, per slot: {source offset in the half-sphere arrays, kind
+    // (0 = stick of the half sphere, 1 = its mirror, 2 = the (0, 0) stick),
+    // -lmin of the (0, 0) stick, index in the group of the mirror stick}
+    const int4 *gam;
 };
 
 struct Geometry {
@@ -32,6 +36,7 @@ struct Geometry {
     int resident_plane_wgs; // plane workgroups resident at once on the device
     int nsub;       // density: band subsets per launch
     int group_cap;  // most sticks in one group (over all segments)
+    int gamma;      // real mode: a launch band is a pair of real bands
     double inv_n;   // 1 / (N1 N2 N3)
 };
 
@@ -48,6 +53,7 @@ struct Seg {
     int nst, npw, ngroups;
     int slot_off, group_off, col_off; // first row in slot_info, groups, cols
     int band_lo, nb, blk_lo;
+    int nbr;          // real mode: real bands from `in` / `out` (2 nb or 2 nb - 1)
 };
 struct Launch {
     int nseg;  // segments in use (1 .. kMaxSeg)

@@ -118,6 +118,46 @@ static bool reciprocal_rows(const double A[9], double B[9])
     return true;
 }
 
+// Real (gamma) mode: psi real <=> c(-g) = conj(c(g)), so only the half sphere
+// H = {h > 0} u {h = 0, k > 0} u {h = k = 0, l >= 0} is stored (canonical order
+// restricted to H).  Per stick: its mirror stick (-h, -k) and the offset of
+// its part of H in the half storage (for the (0, 0) stick: of l = 0).
+static vloc_status build_gamma_tables(HostPlan &p, std::string &err)
+{
+    const int64_t nst = p.nst();
+    const int32_t kspan = p.kmax - p.kmin + 1;
+    std::vector<int32_t> at((size_t)(p.hmax - p.hmin + 1) * kspan, -1);
+    for (int64_t i = 0; i < nst; ++i)
+        at[(size_t)(p.sticks[i].h - p.hmin) * kspan + (p.sticks[i].k - p.kmin)] = (int32_t)i;
+    p.mirror.assign(nst, -1);
+    p.half_off.assign(nst, -1);
+    p.half_hkl.clear();
+    for (int64_t i = 0; i < nst; ++i) {
+        const Stick &s = p.sticks[i];
+        const int32_t mh = -s.h, mk = -s.k;
+        int32_t m = -1;
+        if (mh >= p.hmin && mh <= p.hmax && mk >= p.kmin && mk <= p.kmax)
+            m = at[(size_t)(mh - p.hmin) * kspan + (mk - p.kmin)];
+        if (m < 0 || p.sticks[m].count != s.count ||
+            p.sticks[m].lmin != -(s.lmin + s.count - 1)) {
+            err = "internal: the sphere is not symmetric under g -> -g";
+            return VLOC_E_SPHERE;
+        }
+        p.mirror[i] = m;
+        const bool zero = s.h == 0 && s.k == 0;
+        if (zero || s.h > 0 || (s.h == 0 && s.k > 0)) {
+            const int32_t l0 = zero ? 0 : s.lmin;
+            p.half_off[i] = (int32_t)(p.half_hkl.size() / 3);
+            for (int32_t l = l0; l < s.lmin + s.count; ++l) {
+                p.half_hkl.push_back(s.h);
+                p.half_hkl.push_back(s.k);
+                p.half_hkl.push_back(l);
+            }
+        }
+    }
+    return VLOC_OK;
+}
+
 vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cell[9], double ecut,
                             const double k[3], const vloc_options *opt, std::string &err,
                             const Occupied *cover)
@@ -139,9 +179,15 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         p.opt.plane_rows < 0 || p.opt.plane_threads < 0 || p.opt.plane_threads > 512 ||
         (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
         p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
-        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 2) {
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 2 || p.opt.gamma < 0 ||
+        p.opt.gamma > 1) {
         err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64, "
-              "plane_xwaves <= plane_threads / 64, plane_xmode 0..2)";
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..2, gamma 0..1)";
+        return VLOC_E_INVALID;
+    }
+    p.gamma = p.opt.gamma != 0;
+    if (p.gamma && (!k || k[0] != 0.0 || k[1] != 0.0 || k[2] != 0.0)) {
+        err = "the real (gamma) mode needs k = 0";
         return VLOC_E_INVALID;
     }
     for (int i = 0; i < 3; ++i) {
@@ -284,31 +330,55 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
                                          : std::max(1, want_threads / tasks_per_stick);
     p.group_cap = std::min<int32_t>(p.group_cap, (int32_t)p.sticks.size());
     p.ldz = Lz + 1;
-    p.stick_threads = (int)std::min<int64_t>(
-        512, std::max<int64_t>(64, ((int64_t)std::min<int64_t>(p.group_cap, p.nst()) *
-                                        tasks_per_stick + 63) / 64 * 64));
     const int64_t nst = p.nst();
-    p.ngroups = (int32_t)((nst + p.group_cap - 1) / p.group_cap);
+
+    // ---- units of the deal: one stick, or in the real (gamma) mode a stick of
+    // the half sphere with its mirror (-h, -k), which the stick kernels need in
+    // one workgroup; the (0, 0) stick is its own mirror
+    std::vector<std::vector<int32_t>> units;
+    if (p.gamma) {
+        vloc_status s = build_gamma_tables(p, err);
+        if (s != VLOC_OK) return s;
+        for (int64_t i = 0; i < nst; ++i) {
+            const Stick &st = p.sticks[i];
+            if (st.h == 0 && st.k == 0)
+                units.push_back({(int32_t)i});
+            else if (st.h > 0 || (st.h == 0 && st.k > 0))
+                units.push_back({(int32_t)i, p.mirror[i]});
+        }
+        // a group holds whole units: at most group_cap / 2 pairs
+        p.group_cap = 2 * std::max<int32_t>(1, p.group_cap / 2);
+    } else {
+        for (int64_t i = 0; i < nst; ++i) units.push_back({(int32_t)i});
+    }
+    const int64_t nunits = (int64_t)units.size();
+    const int32_t upg = p.gamma ? p.group_cap / 2 : p.group_cap; // units per group
+    p.ngroups = (int32_t)((nunits + upg - 1) / upg);
+    p.stick_threads = (int)std::min<int64_t>(
+        512, std::max<int64_t>(64, ((int64_t)std::min<int64_t>(p.group_cap, nst) *
+                                        tasks_per_stick + 63) / 64 * 64));
 
     // ---- deal (Sec. 3.2): sort by descending count, ties in canonical order
-    std::vector<int32_t> order(nst);
+    std::vector<int32_t> order(nunits);
     std::iota(order.begin(), order.end(), 0);
     if (p.opt.deal != VLOC_DEAL_CONTIGUOUS)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return p.sticks[a].count > p.sticks[b].count;
+            return p.sticks[units[a][0]].count > p.sticks[units[b][0]].count;
         });
     p.group_of_stick.assign(nst, 0);
     std::vector<std::vector<int32_t>> members(p.ngroups);
-    for (int64_t r = 0; r < nst; ++r) {
+    for (int64_t r = 0; r < nunits; ++r) {
         int32_t g;
         if (p.opt.deal == VLOC_DEAL_CONTIGUOUS) {
-            g = (int32_t)(r / p.group_cap);
+            g = (int32_t)(r / upg);
         } else {
             g = (int32_t)(r % p.ngroups);
             if (p.opt.deal == VLOC_DEAL_SNAKE && ((r / p.ngroups) & 1)) g = p.ngroups - 1 - g;
         }
-        p.group_of_stick[order[r]] = g;
-        members[g].push_back(order[r]);
+        for (int32_t s : units[order[r]]) {
+            p.group_of_stick[s] = g;
+            members[g].push_back(s);
+        }
     }
     p.stick_of_slot.clear();
     p.group_start.assign(p.ngroups, 0);

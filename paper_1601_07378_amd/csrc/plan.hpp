@@ -56,7 +56,16 @@ struct HostPlan {
     int32_t plane_xq = 0;               // > 0: quad x pass, N1 = 4 plane_xq
     std::vector<int32_t> col_kmin, col_kcnt; // per occupied x-plane k range
 
+    // real (gamma) mode: coefficients of the half sphere only, two bands per
+    // complex transform
+    bool gamma = false;
+    std::vector<int32_t> half_hkl;  // half sphere, canonical order
+    std::vector<int32_t> mirror;    // stick -> stick (-h, -k)
+    std::vector<int32_t> half_off;  // stick -> offset of its half-sphere run (or -1)
+
     int64_t npw() const { return (int64_t)hkl.size() / 3; }
+    // coefficients per band in the caller's arrays
+    int64_t npw_io() const { return gamma ? (int64_t)half_hkl.size() / 3 : npw(); }
     int64_t nst() const { return (int64_t)sticks.size(); }
     int elem_bytes() const { return opt.precision == VLOC_F32 ? 8 : 16; }
 };

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("sticks_per_group", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
                 ("plane_rows", ctypes.c_int32), ("plane_threads", ctypes.c_int32),
                 ("plane_xwaves", ctypes.c_int32), ("plane_xmode", ctypes.c_int32),
-                ("split", ctypes.c_int32 * 3)]
+                ("split", ctypes.c_int32 * 3), ("gamma", ctypes.c_int32)]
 
 
 _lib = None
@@ -131,14 +131,16 @@ def _f64(a):
 
 def make_options(precision: str = "f64", deal: str = "greedy", sticks_per_group: int = 0,
                  band_chunk: int = 0, plane_rows: int = 0, plane_threads: int = 0,
-                 plane_xwaves: int = 0, plane_xmode: int = 0, split=(0, 0, 0)) -> Options:
+                 plane_xwaves: int = 0, plane_xmode: int = 0, split=(0, 0, 0),
+                 gamma: bool = False) -> Options:
     """Plan options (zeros = automatic); `split` gives the first codelet length
-    L1 of each axis' L = L1 * L2 split."""
+    L1 of each axis' L = L1 * L2 split; `gamma` selects the real mode (k = 0,
+    half-sphere coefficients, two bands per complex transform)."""
     if precision not in ("f64", "f32"):
         raise ValueError("precision must be 'f64' or 'f32'")
     return Options(VLOC_F64 if precision == "f64" else VLOC_F32, DEALS[deal], sticks_per_group,
                    band_chunk, plane_rows, plane_threads, plane_xwaves, plane_xmode,
-                   (ctypes.c_int32 * 3)(*[int(s) for s in split]))
+                   (ctypes.c_int32 * 3)(*[int(s) for s in split]), 1 if gamma else 0)
 
 
 class Plan:

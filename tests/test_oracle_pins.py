@@ -364,3 +364,70 @@ def test_sign_reflection_identity():
     c_ref[:, perm] = c
     out_ref = oracle.apply(grid, cell, ecut, mk, c_ref, V)
     assert relerr(out_flip, out_ref[:, perm]) < 1e-13
+
+
+# ------------------------------------------------- real (gamma) mode oracle
+
+def test_gamma_half_sphere_counts():
+    for ecut, npw in ((18.0, 925), (288.0, 57777)):
+        hkl = oracle.sphere_py(synth.cubic_cell(), ecut)
+        assert hkl.shape[0] == npw
+        m = oracle.half_mask(hkl)
+        assert m.sum() == (npw + 1) // 2
+        # H and -H partition the sphere minus the origin
+        neg = {tuple((-g).tolist()) for g in hkl[m]}
+        assert len(neg & {tuple(g.tolist()) for g in hkl[m]}) == 1  # only g = 0
+
+
+def test_gamma_expansion_gives_real_psi():
+    grid, cell, ecut = (24, 24, 24), synth.cubic_cell(), 18.0
+    hkl = oracle.sphere_py(cell, ecut)
+    ch = synth.coefficients(hkl[oracle.half_mask(hkl)], 3)
+    psi = oracle.g2r(grid, cell, ecut, (0, 0, 0), oracle.expand_half(hkl, ch))
+    assert np.abs(psi.imag).max() <= 1e-13 * np.abs(psi.real).max()
+    assert np.abs(psi.real).max() > 1e-3
+
+
+def test_gamma_apply_brute_force_tiny():
+    """Closed form of the real mode on a 6^3 grid: psi(j) = Re c(0) +
+    2 Re sum_{g in H, g != 0} c(g) e^{-2 pi i g.j/N}, out(g) = (1/N) sum_j
+    e^{+2 pi i g.j/N} V(j) psi(j) for g in H."""
+    grid, cell, ecut = (6, 6, 6), synth.cubic_cell(), 2.0
+    hkl = oracle.sphere_py(cell, ecut)
+    m = oracle.half_mask(hkl)
+    H = hkl[m]
+    rng = np.random.default_rng(11)
+    ch = rng.standard_normal((2, H.shape[0])) + 1j * rng.standard_normal((2, H.shape[0]))
+    V = rng.uniform(0.5, 1.5, 216)
+    N = 216
+    j3, j2, j1 = np.meshgrid(np.arange(6), np.arange(6), np.arange(6), indexing="ij")
+    J = np.stack([j1.ravel(), j2.ravel(), j3.ravel()], axis=1)  # x fastest
+    ph = np.exp(-2j * np.pi * (H @ J.T) / 6.0)                  # [g in H][j]
+    zero = (H == 0).all(axis=1)
+    ref = []
+    for b in range(2):
+        c = ch[b].copy()
+        psi = np.real(c[zero]).sum() + 2 * np.real(c[~zero] @ ph[~zero])
+        ref.append((np.conj(ph) @ (V * psi)) / N)
+    got = oracle.apply_gamma(grid, cell, ecut, ch, V)
+    assert np.abs(got - np.array(ref)).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_gamma_output_symmetry_and_real_origin():
+    grid, cell, ecut = (24, 24, 24), synth.cubic_cell(), 18.0
+    hkl = oracle.sphere_py(cell, ecut)
+    m = oracle.half_mask(hkl)
+    ch = synth.coefficients(hkl[m], 2)
+    V = synth.potential(grid, 4)
+    full = oracle.apply(grid, cell, ecut, (0, 0, 0), oracle.expand_half(hkl, ch), V)
+    index = {tuple(g): i for i, g in enumerate(hkl.tolist())}
+    mirror = np.array([index[tuple((-g).tolist())] for g in hkl])
+    assert np.abs(full[:, mirror] - np.conj(full)).max() <= 1e-14 * np.abs(full).max()
+    # Im c(0) is ignored
+    ch2 = ch.copy()
+    z = np.nonzero((hkl[m] == 0).all(axis=1))[0]
+    ch2[:, z] += 0.7j
+    a = oracle.apply_gamma(grid, cell, ecut, ch, V)
+    b = oracle.apply_gamma(grid, cell, ecut, ch2, V)
+    assert np.array_equal(a, b)
+    assert np.abs(a[:, z].imag).max() <= 1e-15 * np.abs(a).max()

@@ -171,3 +171,46 @@ def test_layout_defaults():
     assert pq.layout()["plane_xmode"] == 2 and pq.layout()["plane_lds_bytes"] == 49 * 97 * 16
     with pytest.raises(vloc.VlocError):
         vloc.Plan((16, 18, 20), SKEW, 12.0, plane_xmode=2)
+
+
+# ------------------------------------------------------------ real mode
+
+@pytest.mark.parametrize("grid,ecut", [((24, 24, 24), 18.0), ((96, 96, 96), 288.0),
+                                       ((15, 9, 10), 5.0)])
+def test_gamma_plan_half_sphere_and_paired_deal(grid, ecut):
+    cell = synth.cubic_cell() if grid[0] != 15 else SKEW * np.array([[1.0], [0.6], [0.7]])
+    p = vloc.Plan(grid, cell, ecut, gamma=True)
+    full = oracle.sphere_py(cell, ecut)
+    half = full[oracle.half_mask(full)]
+    assert np.array_equal(p.gvectors(), half) and p.npw == half.shape[0]
+    st = p.sticks()
+    assert np.array_equal(st.astype(np.int64), oracle.sticks(full))
+    grp = p.stick_groups()
+    index = {(h, k): i for i, (h, k) in enumerate(st[:, :2].tolist())}
+    for i, (h, k) in enumerate(st[:, :2].tolist()):
+        assert grp[i] == grp[index[(-h, -k)]]      # a stick and its mirror share a group
+    # the deal of pairs: greedy order of the half-sphere sticks' counts
+    loads = p.balance()
+    assert loads.sum() == full.shape[0]
+    assert loads.max() - loads.min() <= 2 * st[:, 3].max()
+
+
+def test_gamma_validation():
+    cell = synth.cubic_cell()
+    with pytest.raises(vloc.VlocError) as e:
+        vloc.Plan((24, 24, 24), cell, 18.0, (0.25, 0, 0), gamma=True)
+    assert e.value.status == vloc.VLOC_E_INVALID
+    with pytest.raises(vloc.VlocError):
+        vloc.Batch((24, 24, 24), cell, 18.0, [(0, 0, 0)], gamma=True)
+    L = vloc.lib()
+    p = vloc.Plan((24, 24, 24), cell, 18.0, gamma=True)
+    fake = ctypes.c_void_p(0x10000000)
+    other = ctypes.c_void_p(0x20000000)
+    assert L.vloc_g2r(p._h, fake, 1, other) == vloc.VLOC_E_INVALID
+    assert L.vloc_r2g(p._h, fake, 1, other) == vloc.VLOC_E_INVALID
+    assert L.vloc_band_dot(p._h, fake, other, 1, other) == vloc.VLOC_E_INVALID
+    assert L.vloc_density(p._h, fake, 1, other, None, other) == vloc.VLOC_E_INVALID
+    assert L.vloc_scale_bands(p._h, fake, 1, None, None, 1.0, other) == vloc.VLOC_E_INVALID
+    # apply's alias check covers the two half-sphere bands (2 x 463 coefficients)
+    assert L.vloc_apply(p._h, fake, 2, ctypes.c_void_p(0x40000000),
+                        ctypes.c_void_p(0x10000000 + 16 * 925)) == vloc.VLOC_E_ALIAS

@@ -77,13 +77,17 @@ typedef struct {
     int32_t plane_rows;       /* rows per x-pass batch of one wavefront in the plane
                                  kernel; 0 = automatic                             */
     int32_t plane_threads;    /* threads per plane workgroup (64..512, multiple of
-                                 64); 0 = automatic                                */
+                                 64; FP64 plans up to 1024 for vloc_apply and
+                                 vloc_density); 0 = automatic                      */
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
-    int32_t plane_xmode;      /* x pass of the plane kernel: 0 = automatic, 1 = row
-                                 buffers in LDS, 2 = one lane quad per row (needs
-                                 N1 in {24, 72, 80, 96} with the matching y split
-                                 and N2 <= 128)                                    */
+    int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where
+                                 the whole plane fits in LDS, else 1); 1 = the
+                                 occupied x-planes plus per-wavefront row buffers;
+                                 2 = occupied x-planes, one lane quad per x row
+                                 (needs N1 in {24, 72, 80, 96} with the matching y
+                                 split and N2 <= 128); 3 = the whole plane, x pass
+                                 in place (N1 (N2 + 1) elements <= 160 KiB)        */
     int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
                                  each axis (x, y, z); 0 = automatic (the most
                                  balanced split); else L1 and L / L1 must both be
@@ -152,7 +156,8 @@ vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
 /* Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
  * sticks_per_group, band_chunk}; out[8..13] = {plane_rows, plane_threads,
  * plane_lds_bytes, nxo, plane_xwaves, plane_xmode} where nxo is the number of
- * occupied x-planes and plane_xmode is 1 (row buffers) or 2 (lane quads). */
+ * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads) or 3
+ * (whole plane). */
 vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14]);
 
 /* ------------------------------------------------------- kernel timing */

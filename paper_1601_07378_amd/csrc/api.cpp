@@ -39,6 +39,7 @@ struct Engine {
     size_t S_bytes = 0;
     double *d_partial = nullptr; // density partial planes
     size_t partial_bytes = 0;
+    void *d_VT = nullptr;        // potential in the full-plane kernel's order
     Geometry geo{};
     // kernel timing: events[4*i .. 4*i+3] bracket K1, K2, K3 of launch i
     bool timing = false;
@@ -100,6 +101,7 @@ void free_device(Engine &E)
     for (void *&t : E.d_tw) free_ptr(t);
     free_ptr(E.d_S);
     free_ptr(E.d_partial);
+    free_ptr(E.d_VT);
     E.partial_bytes = 0;
     E.S_bytes = 0;
     E.uploaded = false;
@@ -151,7 +153,10 @@ vloc_status upload(Engine &E)
             if (lm < 0) lm += m->grid[2];
             int kp = st.k % m->grid[1];
             if (kp < 0) kp += m->grid[1];
-            slot.push_back(make_int4(st.offset, st.count, lm, (st.h - m->hmin) * m->ldy + kp));
+            // plane position: occupied column h - hmin, or in the full plane column h mod N1
+            int col = st.h - m->hmin;
+            if (m->plane_full) col = ((st.h % m->grid[0]) + m->grid[0]) % m->grid[0];
+            slot.push_back(make_int4(st.offset, st.count, lm, col * m->ldy + kp));
         }
         for (int g = 0; g < m->ngroups; ++g) {
             groups.push_back(make_int2(m->group_start[g], m->group_size[g]));
@@ -180,6 +185,10 @@ vloc_status upload(Engine &E)
     if ((e = upload_vec(E.d_groups, groups)) != hipSuccess) goto devfail;
     if ((e = upload_vec(E.d_cols, cols)) != hipSuccess) goto devfail;
     if (!gam.empty() && (e = upload_vec(E.d_gam, gam)) != hipSuccess) goto devfail;
+    if (h.plane_full) {
+        const size_t vbytes = (size_t)h.grid[0] * h.grid[1] * h.grid[2] * (h.elem_bytes() / 2);
+        if ((e = hipMalloc(&E.d_VT, vbytes)) != hipSuccess) goto devfail;
+    }
     {
         const Split *sp[3] = {&h.sx, &h.sy, &h.sz};
         for (int a = 0; a < 3; ++a) {
@@ -228,6 +237,8 @@ vloc_status upload(Engine &E)
         g.zx = h.zx;
         g.zy = h.zy;
         g.zz = h.zz;
+        g.fx = h.fx;
+        g.full = h.plane_full ? 1 : 0;
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E.device) !=
                 hipSuccess ||
@@ -394,6 +405,12 @@ vloc_status run_launches(Engine &E, int mode, const std::vector<Launch> &ls, con
     t.wts = wts;
     hipError_t e;
     int64_t band0 = 0;
+    if (mode == MODE_APPLY && g.full && !ls.empty()) {
+        // the potential in the full-plane kernel's order, once per call
+        if ((e = launch_arrange_v<T>(g, V, E.d_VT, st)) != hipSuccess)
+            return hip_fail(e, "potential arrangement launch");
+        V = E.d_VT;
+    }
     for (const Launch &L : ls) {
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         if (timed) {
@@ -684,7 +701,7 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     s = dispatch(plan, MODE_DENSITY, c, nbands, nullptr, nullptr, w);
     if (s != VLOC_OK) return s;
-    e = launch_density_reduce(E.d_partial, g.nsub, N, g.inv_n, scale, rho, E.stream);
+    e = launch_density_reduce(g, E.d_partial, g.nsub, scale, rho, E.stream);
     return e == hipSuccess ? VLOC_OK : hip_fail(e, "density reduce launch");
 }
 
@@ -748,7 +765,7 @@ vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14])
     int32_t v[14] = {h.sx.L1,      h.sx.L2,         h.sy.L1,      h.sy.L2, h.sz.L1,
                      h.sz.L2,      h.group_cap,     h.band_chunk, h.plane_rows,
                      h.plane_threads, h.plane_lds, h.nxo,        h.plane_xw,
-                     h.plane_xq ? 2 : 1};
+                     h.plane_full ? 3 : (h.plane_xq ? 2 : 1)};
     std::memcpy(out, v, sizeof v);
     return VLOC_OK;
 }

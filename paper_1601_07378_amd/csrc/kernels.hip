@@ -23,6 +23,7 @@
 //            A': task n2 takes positions n2 + L2 k1, multiplies by W_L^{n2 k1},
 //                runs the L1-point DFT and stores x[n2 + L2 n1] in natural order.
 // Between A and B (and B' and A') values cross threads through LDS.
+#include <algorithm>
 #include <type_traits>
 
 #include "dft_codelets.h"
@@ -108,31 +109,26 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 }
 
 // Segment of a launch by a uniform key (stick-kernel block or launch band):
-// the last segment whose first key is <= v.  Fields are copied with
-// compile-time indices so that the descriptor stays in scalar registers.
+// the last segment whose first key is <= v.  The descriptor is read from the
+// kernel-argument segment with a uniform index (scalar loads), not held in
+// registers across the kernel.
 __device__ __forceinline__ Seg seg_by_block(const Launch &L, int v)
 {
-    Seg r = L.seg[0];
-#pragma unroll
-    for (int i = 1; i < kMaxSeg; ++i)
-        if (i < L.nseg && v >= L.seg[i].blk_lo) r = L.seg[i];
-    return r;
+    int s = 0;
+    for (int i = 1; i < L.nseg; ++i)
+        if (v >= L.seg[i].blk_lo) s = i;
+    return L.seg[s];
 }
 __device__ __forceinline__ int seg_index_by_band(const Launch &L, int v)
 {
     int s = 0;
-#pragma unroll
-    for (int i = 1; i < kMaxSeg; ++i)
-        if (i < L.nseg && v >= L.seg[i].band_lo) s = i;
+    for (int i = 1; i < L.nseg; ++i)
+        if (v >= L.seg[i].band_lo) s = i;
     return s;
 }
 __device__ __forceinline__ Seg seg_at(const Launch &L, int s)
 {
-    Seg r = L.seg[0];
-#pragma unroll
-    for (int i = 1; i < kMaxSeg; ++i)
-        if (i == s) r = L.seg[i];
-    return r;
+    return L.seg[s];
 }
 
 // Real mode: the value at position i of a stick's run for the band pair
@@ -514,7 +510,8 @@ __device__ __forceinline__ void quad_twiddle(T *xr, T *xi, int q, int L,
     }
 }
 
-template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY, int XQ>
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY, int XQ,
+          int PF>
 __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t, const Launch &L,
                                            cx<T> *__restrict__ S, const T *__restrict__ V,
                                            cx<T> *__restrict__ psi, long long band0)
@@ -589,7 +586,6 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     // registers while consecutive planes belong to one segment, and their
     // values for the next plane are loaded while the current plane is
     // transformed.
-    constexpr int PF = 4;
     int spos[PF];
     cx<T> sval[PF];
     int spos_seg = -1;
@@ -934,13 +930,409 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     }
 }
 
-// LDS row-buffer variant (any split), up to 512 threads.
+// LDS row-buffer variant (any split), up to 512 threads.  The first 4
+// slots of each thread are prefetched for the next plane (2048 slots).
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY>
 __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, Launch L,
                                                cx<T> *__restrict__ S, const T *__restrict__ V,
                                                cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0>(g, t, L, S, V, psi, band0);
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 4>(g, t, L, S, V, psi, band0);
+}
+
+// The same with up to 1024 threads (16 waves: more latency hiding for FP64,
+// whose plane and row buffers fill the LDS of a CU); 2 prefetched slots per
+// thread, 128 registers per lane.
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY>
+__global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, Launch L,
+                                                     cx<T> *__restrict__ S,
+                                                     const T *__restrict__ V,
+                                                     cx<T> *__restrict__ psi, long long band0)
+{
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 2>(g, t, L, S, V, psi, band0);
+}
+
+// ------------------------------------------------------- K2, full plane
+// Full-plane variant of the plane kernel: LDS holds the whole plane P[x][y]
+// (N1 columns of N2, column stride ldy), so the x pass runs in place on every
+// row and needs no row buffers; its three stages spread over all threads of
+// the workgroup with lanes along the (transposed-order) row index, which keeps
+// LDS accesses contiguous.  The y pass runs on the occupied columns only.
+// Zero masks of the x stage-A groups: ZX = no occupied x (never read, never
+// written back), FX = every x occupied (read and written unconditionally);
+// other groups check occupancy per position.  Non-occupied positions of a row
+// may hold stale values: they are never read as input.  The potential comes
+// pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF>
+__device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
+                                                const Launch &L, cx<T> *__restrict__ S,
+                                                const T *__restrict__ VT,
+                                                cx<T> *__restrict__ psi, long long band0)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *plane = reinterpret_cast<cx<T> *>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int L1x = CX1 ? CX1 : g.L1x, L2x = CX2 ? CX2 : g.L2x;
+    const int L1y = CY1 ? CY1 : g.L1y, L2y = CY2 ? CY2 : g.L2y;
+    const int N1 = CX1 ? CX1 * CX2 : g.N1;
+    const int N2 = CY1 ? CY1 * CY2 : g.N2;
+    const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
+    const int nxo = g.nxo, hx = g.hmin_mod;
+    const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
+    const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
+    const int nb = L.nbt;
+    // column of occupied x-plane hc
+    auto col_of = [&](int hc) {
+        int x = hx + hc;
+        return x >= N1 ? x - N1 : x;
+    };
+    // x occupied?
+    auto occupied = [&](int x) {
+        int r = x - hx;
+        if (r < 0) r += N1;
+        return r < nxo;
+    };
+
+    // work items and persistent XCD-aware schedule as in plane_body
+    constexpr bool DENS = (MODE == MODE_DENSITY);
+    const int nsub = DENS ? g.nsub : 1;
+    const int bps = DENS ? (nb + nsub - 1) / nsub : 1;
+    const int total = DENS ? g.N3 * nsub : nb * g.N3;
+    int j0 = blockIdx.x, jstep = gridDim.x, jend = total;
+    if ((gridDim.x & 7) == 0 && (total & 7) == 0) {
+        const int share = total >> 3, xcd = blockIdx.x & 7;
+        j0 = xcd * share + (blockIdx.x >> 3);
+        jstep = gridDim.x >> 3;
+        jend = (xcd + 1) * share;
+    }
+    auto plane_of = [&](int j, int k, int &zz, int &bb) {
+        if (DENS) {
+            zz = j / nsub;
+            bb = (j - zz * nsub) * bps + k;
+        } else {
+            zz = j / nb;
+            bb = j - zz * nb;
+        }
+    };
+    auto advance = [&](int &j, int &k) -> bool {
+        for (;;) {
+            if (DENS && k + 1 < bps)
+                ++k;
+            else {
+                j += jstep;
+                k = 0;
+            }
+            if (j >= jend) return false;
+            int zz, bb;
+            plane_of(j, k, zz, bb);
+            if (bb < nb) return true;
+            k = bps;
+        }
+    };
+    auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
+    int spos[PF];
+    cx<T> sval[PF];
+    int spos_seg = -1;
+    auto load_pos = [&](int si) {
+        const Seg sg = seg_at(L, si);
+        const int4 *sl_info = t.slot_info + sg.slot_off;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            spos[i] = sl < sg.nst ? sl_info[sl].w : 0;
+        }
+        spos_seg = si;
+    };
+#pragma unroll
+    for (int i = 0; i < PF; ++i) sval[i] = mk<T>(T(0), T(0));
+    load_pos(0);
+    auto prefetch = [&](int zz, int bb) {
+        const Seg sg = seg_at(L, seg_of(bb));
+        const cx<T> *Sj = S + sg.s_off + ((long long)(bb - sg.band_lo) * g.N3 + zz) * sg.nst;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            if (sl < sg.nst) sval[i] = Sj[sl];
+        }
+    };
+    int jc = j0, kc = 0;
+    bool have = jc < jend;
+    if (have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        if (bb >= nb) have = advance(jc, kc);
+    }
+    if (MODE != MODE_R2G && have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        prefetch(zz, bb);
+    }
+
+    for (; have; have = advance(jc, kc)) {
+    int z, bl;
+    plane_of(jc, kc, z, bl);
+    const int si = seg_of(bl);
+    const Seg sg = seg_at(L, si);
+    const int nst = sg.nst;
+    const int4 *slots = t.slot_info + sg.slot_off;
+    const int2 *cols = t.cols + sg.col_off;
+    cx<T> *Sz = S + sg.s_off + ((long long)(bl - sg.band_lo) * g.N3 + z) * nst;
+    if (si != spos_seg) load_pos(si);
+    cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
+    const T *VTz = VT ? VT + (long long)z * N1 * N2 : nullptr;
+    // density partial plane in [x][yp] order
+    double *accz = DENS ? t.partial + ((long long)(bl / bps) * g.N3 + z) * N1 * N2 : nullptr;
+
+    if (MODE != MODE_R2G) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+            if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
+        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
+        __syncthreads();
+        {
+            int jn = jc, kn = kc, zz, bb;
+            if (advance(jn, kn)) {
+                plane_of(jn, kn, zz, bb);
+                prefetch(zz, bb);
+            }
+        }
+        // y forward, stage A (lanes along occupied columns)
+        with_size<CY1>(L1y, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < nxo * L2y; task += nthr) {
+                const int n2 = task / nxo, hc = task - n2 * nxo;
+                const int2 ci = cols[hc];
+                cx<T> *col = plane + col_of(hc) * ldy + n2;
+                T xr[R], xi[R];
+#pragma unroll
+                for (int n1 = 0; n1 < R; ++n1) {
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (!masked<ZY>(n1)) {
+                        int rel = n2 + L2y * n1 - ci.x;
+                        if (rel < 0) rel += N2;
+                        if (rel < ci.y) v = col[L2y * n1];
+                    }
+                    xr[n1] = v.x;
+                    xi[n1] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+                twiddle<R, -1, T>(xr, xi, n2, twy);
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
+            }
+        });
+        __syncthreads();
+        // y forward, stage B
+        with_size<CY2>(L2y, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < nxo * L1y; task += nthr) {
+                const int k1 = task / nxo, hc = task - k1 * nxo;
+                cx<T> *col = plane + col_of(hc) * ldy + L2y * k1;
+                T xr[R], xi[R];
+#pragma unroll
+                for (int n2 = 0; n2 < R; ++n2) {
+                    cx<T> v = col[n2];
+                    xr[n2] = v.x;
+                    xi[n2] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) col[k2] = mk<T>(xr[k2], xi[k2]);
+            }
+        });
+        __syncthreads();
+        // x forward, stage A, in place: row yp, inputs x = n2 + L2x n1
+        with_size<CX1>(L1x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < L2x * N2; task += nthr) {
+                const int n2 = task / N2, yp = task - n2 * N2;
+                cx<T> *row = plane + n2 * ldy + yp;
+                T xr[R], xi[R];
+#pragma unroll
+                for (int n1 = 0; n1 < R; ++n1) {
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (!masked<ZX>(n1)) {
+                        if (masked<FX>(n1) || occupied(n2 + L2x * n1)) v = row[L2x * n1 * ldy];
+                    }
+                    xr[n1] = v.x;
+                    xi[n1] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+                twiddle<R, -1, T>(xr, xi, n2, twx);
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
+            }
+        });
+        __syncthreads();
+    }
+
+    // x stage B: frequencies x = k1 + L1x k2 of row yp, with the potential
+    // (APPLY), the density (DENSITY) or the real-space values (G2R / R2G)
+    with_size<CX2>(L2x, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        for (int task = tid; task < L1x * N2; task += nthr) {
+            const int k1 = task / N2, yp = task - k1 * N2;
+            cx<T> *row = plane + L2x * k1 * ldy + yp;
+            T xr[R], xi[R];
+            T vv[R];
+            if (MODE == MODE_APPLY) {
+                const T *vcol = VTz + (long long)k1 * N2 + yp;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) vv[k2] = vcol[(long long)L1x * k2 * N2];
+            }
+            // natural row index of position yp (psi is [z][y][x])
+            const int y = (yp % L2y) * L1y + yp / L2y;
+            if (MODE == MODE_R2G) {
+                const cx<T> *src = psiz + (long long)y * N1 + k1;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) {
+                    cx<T> v = src[L1x * k2];
+                    xr[k2] = v.x;
+                    xi[k2] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int n2 = 0; n2 < R; ++n2) {
+                    cx<T> v = row[n2 * ldy];
+                    xr[n2] = v.x;
+                    xi[n2] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+            }
+            if (MODE == MODE_G2R) {
+                cx<T> *dst = psiz + (long long)y * N1 + k1;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
+            } else if (MODE == MODE_DENSITY) {
+                const double wb = t.wts[band0 + bl];
+                double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) {
+                    const double a = (double)xr[k2], b = (double)xi[k2];
+                    acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+                }
+            } else {
+                if (MODE == MODE_APPLY) {
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) {
+                        xr[k2] *= vv[k2];
+                        xi[k2] *= vv[k2];
+                    }
+                }
+                Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+                for (int n2 = 0; n2 < R; ++n2) row[n2 * ldy] = mk<T>(xr[n2], xi[n2]);
+            }
+        }
+    });
+    __syncthreads();
+    if (MODE == MODE_G2R || MODE == MODE_DENSITY) continue;
+
+    // x reverse, stage A': occupied outputs only
+    with_size<CX1>(L1x, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        for (int task = tid; task < L2x * N2; task += nthr) {
+            const int n2 = task / N2, yp = task - n2 * N2;
+            cx<T> *row = plane + n2 * ldy + yp;
+            T xr[R], xi[R];
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) {
+                cx<T> v = row[L2x * k1 * ldy];
+                xr[k1] = v.x;
+                xi[k1] = v.y;
+            }
+            twiddle<R, +1, T>(xr, xi, n2, twx);
+            Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+            for (int n1 = 0; n1 < R; ++n1) {
+                if (masked<ZX>(n1)) continue;
+                if (masked<FX>(n1) || occupied(n2 + L2x * n1))
+                    row[L2x * n1 * ldy] = mk<T>(xr[n1], xi[n1]);
+            }
+        }
+    });
+    __syncthreads();
+    // y reverse, stage B'
+    with_size<CY2>(L2y, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        for (int task = tid; task < nxo * L1y; task += nthr) {
+            const int k1 = task / nxo, hc = task - k1 * nxo;
+            cx<T> *col = plane + col_of(hc) * ldy + L2y * k1;
+            T xr[R], xi[R];
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                cx<T> v = col[k2];
+                xr[k2] = v.x;
+                xi[k2] = v.y;
+            }
+            Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+            for (int n2 = 0; n2 < R; ++n2) col[n2] = mk<T>(xr[n2], xi[n2]);
+        }
+    });
+    __syncthreads();
+    // y reverse, stage A': only stick positions are kept
+    with_size<CY1>(L1y, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        for (int task = tid; task < nxo * L2y; task += nthr) {
+            const int n2 = task / nxo, hc = task - n2 * nxo;
+            const int2 ci = cols[hc];
+            cx<T> *col = plane + col_of(hc) * ldy + n2;
+            T xr[R], xi[R];
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) {
+                cx<T> v = col[L2y * k1];
+                xr[k1] = v.x;
+                xi[k1] = v.y;
+            }
+            twiddle<R, +1, T>(xr, xi, n2, twy);
+            Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+            for (int n1 = 0; n1 < R; ++n1) {
+                if (masked<ZY>(n1)) continue;
+                int rel = n2 + L2y * n1 - ci.x;
+                if (rel < 0) rel += N2;
+                if (rel < ci.y) col[L2y * n1] = mk<T>(xr[n1], xi[n1]);
+            }
+        }
+    });
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+        if (tid + i * nthr < nst) Sz[tid + i * nthr] = plane[spos[i]];
+    for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = plane[slots[sl].w];
+    __syncthreads(); // the next plane's scatter overwrites P
+    }
+}
+
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
+          int MAXT>
+__global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, Launch L,
+                                                     cx<T> *__restrict__ S,
+                                                     const T *__restrict__ VT,
+                                                     cx<T> *__restrict__ psi, long long band0)
+{
+    // prefetched slots per thread cover 2048 slots
+    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT>(
+        g, t, L, S, VT, psi, band0);
+}
+
+// VT[z][x][yp] = V[z][y][x], yp = L2y (y mod L1y) + y / L1y: the potential in
+// the order the full-plane kernel reads it (contiguous along yp).
+template <typename T>
+__global__ void k_arrange_v(const T *__restrict__ V, T *__restrict__ VT, int N1, int N2, int N3,
+                            int L1y, int L2y)
+{
+    const long long n = (long long)N1 * N2 * N3;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long zx = i / N2;
+        const int yp = (int)(i - zx * N2);
+        const long long z = zx / N1;
+        const int x = (int)(zx - z * N1);
+        const int y = (yp % L2y) * L1y + yp / L2y;
+        VT[i] = V[(z * N2 + y) * N1 + x];
+    }
 }
 
 // Quad variant: no row buffer, so the occupied plane is the only LDS and two
@@ -950,7 +1342,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per
 void k_plane_quad(Geometry g, DevTables t, Launch L, cx<T> *__restrict__ S,
                   const T *__restrict__ V, cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ>(g, t, L, S, V, psi, band0);
+    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ, 4>(g, t, L, S, V, psi, band0);
 }
 
 // ------------------------------------------------------------ launchers
@@ -1030,13 +1422,19 @@ static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, cons
                                      void *S, const void *V, void *psi, int64_t band0,
                                      int threads, int lds, hipStream_t st)
 {
-    auto kern = k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>;
-    hipError_t e = allow_lds(kern, (size_t)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g, t,
-                       L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
-                       reinterpret_cast<cx<T> *>(psi), (long long)band0);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, (size_t)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g,
+                           t, L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                           reinterpret_cast<cx<T> *>(psi), (long long)band0);
+        return hipGetLastError();
+    };
+    if (threads <= 512) return go(k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
+    // wide workgroups: compiled for FP64 application and density only
+    if constexpr (std::is_same<T, double>::value && (MODE == MODE_APPLY || MODE == MODE_DENSITY))
+        return go(k_plane_wide<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int MODE, int XQ, int Y1, int Y2>
@@ -1053,13 +1451,53 @@ static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, const
     return hipGetLastError();
 }
 
+template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY>
+static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const Launch &L,
+                                    void *S, const void *VT, void *psi, int64_t band0,
+                                    int threads, int lds, hipStream_t st)
+{
+    auto go = [&](auto kern, int nthr) {
+        hipError_t e = allow_lds(kern, (size_t)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(nthr), (size_t)lds, st, g, t,
+                           L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(VT),
+                           reinterpret_cast<cx<T> *>(psi), (long long)band0);
+        return hipGetLastError();
+    };
+    // more than 512 threads: compiled for FP64 application and density; the
+    // diagnostic transforms run the same body on 512 threads
+    if constexpr (std::is_same<T, double>::value && (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
+        if (threads > 768)
+            return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024>, threads);
+        if (threads > 512)
+            return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768>, threads);
+    }
+    return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512>, threads < 512 ? threads : 512);
+}
+
 // Specialised line splits for the common grids; any other split runs the same
-// kernel with runtime sizes.
+// kernel with runtime sizes.  A specialisation serves every plan whose zero
+// masks contain its own.
 template <typename T, int MODE>
 static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const Launch &L,
                                     void *S, const void *V, void *psi, int64_t band0,
                                     int threads, int lds, hipStream_t st)
 {
+    if (g.full) {
+#define VLOC_FULL_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                 \
+        if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&      \
+            (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                               \
+            return launch_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY>(g, t, L, S, V, psi,      \
+                                                                         band0, threads, lds, st);
+        VLOC_FULL_CASE(8, 12, 8, 12, 0x38, 0xC3, 0x38)
+        VLOC_FULL_CASE(8, 9, 8, 12, 0x38, 0xC3, 0x3C)
+        VLOC_FULL_CASE(8, 16, 8, 16, 0x38, 0xC3, 0x38)
+        VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
+        VLOC_FULL_CASE(4, 6, 4, 6, 0x4, 0x9, 0x4)
+#undef VLOC_FULL_CASE
+        return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
+                                                               lds, st);
+    }
     if constexpr (MODE != MODE_DENSITY) if (g.xq) {
 #define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
         if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
@@ -1114,6 +1552,17 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
     }
 }
 
+template <typename T>
+hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStream_t st)
+{
+    const long long n = (long long)g.N1 * g.N2 * g.N3;
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_arrange_v<T>, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<const T *>(V), reinterpret_cast<T *>(VT), g.N1, g.N2,
+                       g.N3, g.L1y, g.L2y);
+    return hipGetLastError();
+}
+
 #define VLOC_INSTANTIATE(T)                                                                       \
     template hipError_t launch_stick_fwd<T>(const Geometry &, const DevTables &, const Launch &, \
                                             void *, int, hipStream_t);                           \
@@ -1121,8 +1570,14 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
                                             const void *, int, hipStream_t);                     \
     template hipError_t launch_plane<T>(const Geometry &, const DevTables &, const Launch &, int, \
                                         void *, const void *, void *, int64_t, int, int,         \
-                                        hipStream_t);
+                                        hipStream_t);                                            \
+    template hipError_t launch_arrange_v<T>(const Geometry &, const void *, void *, hipStream_t);
+// The build compiles this file once per precision (in parallel).
+#if !defined(VLOC_ONLY_F32)
 VLOC_INSTANTIATE(double)
+#endif
+#if !defined(VLOC_ONLY_F64)
 VLOC_INSTANTIATE(float)
+#endif
 
 } // namespace vloc

@@ -33,6 +33,8 @@ struct Geometry {
     int xw;         // wavefronts taking part in the x pass
     int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
+    int fx;         // x stage-A groups whose every position is occupied
+    int full;       // plane kernel holds the whole plane (x pass in place)
     int resident_plane_wgs; // plane workgroups resident at once on the device
     int nsub;       // density: band subsets per launch
     int group_cap;  // most sticks in one group (over all segments)
@@ -77,7 +79,9 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
                         hipStream_t st);
 // Density helpers (reduce.hip): FP64 reductions and band scaling.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
-hipError_t launch_density_reduce(const double *partial, int nsub, int64_t n, double inv_n,
+// partial planes in [z][y][x] order, or with full != 0 in the full-plane
+// kernel's [z][x][yp] order
+hipError_t launch_density_reduce(const Geometry &g, const double *partial, int nsub,
                                  const double *scale, double *rho, hipStream_t st);
 template <typename T>
 hipError_t launch_band_dot(const void *a, const void *b, int64_t npw, int64_t nb, double *out,
@@ -88,6 +92,10 @@ template <typename T>
 hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const double *w,
                               const double *scale, double factor, void *y, hipStream_t st);
 
+// VT[z][x][yp] = V[z][y][x] with yp the row's position after the y pass (the
+// full-plane kernel's order of the potential).
+template <typename T>
+hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStream_t st);
 // K3: stick z-transforms (r -> G direction) with 1/N, gathering into each
 // segment's out.
 template <typename T>

@@ -99,6 +99,23 @@ static int32_t zero_mask(const Split &s, long lo, long hi)
     return m;
 }
 
+// Bit n1 is set when every position of the stage-A group {n2 + L2 n1} is
+// occupied (lies in [lo, hi] taken mod L).
+static int32_t full_mask(const Split &s, long lo, long hi)
+{
+    int32_t m = 0;
+    for (int n1 = 0; n1 < s.L1; ++n1) {
+        bool all = true;
+        for (int n2 = 0; n2 < s.L2 && all; ++n2) {
+            long pos = n2 + (long)s.L2 * n1;
+            long r = ((pos - lo) % s.L + s.L) % s.L;
+            all = lo + r <= hi;
+        }
+        if (all) m |= 1 << n1;
+    }
+    return m;
+}
+
 static bool reciprocal_rows(const double A[9], double B[9])
 {
     double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
@@ -176,13 +193,15 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         return VLOC_E_INVALID;
     }
     if (p.opt.sticks_per_group < 0 || p.opt.sticks_per_group > 64 || p.opt.band_chunk < 0 ||
-        p.opt.plane_rows < 0 || p.opt.plane_threads < 0 || p.opt.plane_threads > 512 ||
+        p.opt.plane_rows < 0 || p.opt.plane_threads < 0 || p.opt.plane_threads > 1024 ||
         (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
+        (p.opt.plane_threads > 512 && p.opt.precision != VLOC_F64) ||
         p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
-        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 2 || p.opt.gamma < 0 ||
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 3 || p.opt.gamma < 0 ||
         p.opt.gamma > 1) {
-        err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64, "
-              "plane_xwaves <= plane_threads / 64, plane_xmode 0..2, gamma 0..1)";
+        err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64 "
+              "(FP64: up to 1024), "
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..3, gamma 0..1)";
         return VLOC_E_INVALID;
     }
     p.gamma = p.opt.gamma != 0;
@@ -316,6 +335,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     }
     p.nxo = p.hmax - p.hmin + 1;
     p.zx = zero_mask(p.sx, p.hmin, p.hmax);
+    p.fx = full_mask(p.sx, p.hmin, p.hmax);
     p.zy = zero_mask(p.sy, p.kmin, p.kmax);
     p.zz = zero_mask(p.sz, lmin, lmax);
 
@@ -464,7 +484,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         // measured slower than the row buffers in both precisions at 96^3, so
         // only used when asked for
         bool want = p.opt.plane_xmode == 2;
-        if (p.opt.plane_xmode == 2 && !fits) {
+        if (p.opt.plane_xmode == 2 && (!fits || p.opt.plane_threads > 512)) {
             err = "quad x pass not available for this grid";
             return VLOC_E_INVALID;
         }
@@ -476,6 +496,26 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             p.plane_rb = 1;
             p.plane_rows = 0;
             p.plane_lds = (int32_t)plane_bytes;
+        }
+    }
+    // Full plane: the whole plane in LDS and the x pass in place over all
+    // threads (no row buffers).  The default wherever it fits; the row-buffer
+    // layout otherwise or when asked for.
+    {
+        const int64_t full_bytes = (int64_t)grid[0] * p.ldy * es;
+        const bool fits = full_bytes <= lds_max;
+        if (p.opt.plane_xmode == 3 && !fits) {
+            err = "the full plane does not fit in LDS (plane_xmode 3)";
+            return VLOC_E_INVALID;
+        }
+        if (fits && (p.opt.plane_xmode == 3 || p.opt.plane_xmode == 0)) {
+            p.plane_full = true;
+            p.plane_xq = 0;
+            p.plane_xw = 0;
+            p.plane_rb = 0;
+            p.plane_rows = 0;
+            p.plane_lds = (int32_t)full_bytes;
+            p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads : (es == 16 ? 1024 : 512);
         }
     }
     // per occupied x-plane: first k (mod N2) and number of k on sticks

@@ -36,6 +36,8 @@ struct HostPlan {
     int32_t hmin = 0, hmax = 0, kmin = 0, kmax = 0, nxo = 0;
     int32_t lmin = 0, lmax = 0;
     int32_t zx = 0, zy = 0, zz = 0; // stage-A input groups that are zero on every line
+    int32_t fx = 0;                 // x stage-A groups whose every position is occupied
+    bool plane_full = false;        // plane kernel holds the whole plane (x pass in place)
 
     // deal of sticks to groups; slots are numbered so that each group's
     // sticks are contiguous

@@ -30,16 +30,28 @@ __global__ void k_fill_f64(double *x, long long n, double v)
         x[i] = v;
 }
 
-// rho[j] += scale * inv_n * sum_{s < nsub} partial[s][j], s ascending.
-__global__ void k_density_reduce(const double *__restrict__ partial, int nsub, long long n,
-                                 double inv_n, const double *__restrict__ scale,
-                                 double *__restrict__ rho)
+// rho[j] += scale * inv_n * sum_{s < nsub} partial[s][j'], s ascending, where
+// j = (z, y, x) and j' is j itself, or with full != 0 the full-plane kernel's
+// index (z, x, yp), yp = L2y (y mod L1y) + y / L1y.
+__global__ void k_density_reduce(const double *__restrict__ partial, int nsub, int N1, int N2,
+                                 int N3, int full, int L1y, int L2y, double inv_n,
+                                 const double *__restrict__ scale, double *__restrict__ rho)
 {
     const double f = inv_n * (scale ? scale[0] : 1.0);
+    const long long n = (long long)N1 * N2 * N3;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
+        long long src = i;
+        if (full) {
+            const long long zy = i / N1;
+            const int x = (int)(i - zy * N1);
+            const long long z = zy / N2;
+            const int y = (int)(zy - z * N2);
+            const int yp = L2y * (y % L1y) + y / L1y;
+            src = (z * N1 + x) * N2 + yp;
+        }
         double acc = 0.0;
-        for (int s = 0; s < nsub; ++s) acc += partial[(long long)s * n + i];
+        for (int s = 0; s < nsub; ++s) acc += partial[(long long)s * n + src];
         rho[i] += f * acc;
     }
 }
@@ -121,12 +133,13 @@ hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_density_reduce(const double *partial, int nsub, int64_t n, double inv_n,
+hipError_t launch_density_reduce(const Geometry &g, const double *partial, int nsub,
                                  const double *scale, double *rho, hipStream_t st)
 {
+    const int64_t n = (int64_t)g.N1 * g.N2 * g.N3;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_density_reduce, dim3(grid_for(n)), dim3(256), 0, st, partial, nsub,
-                       (long long)n, inv_n, scale, rho);
+                       g.N1, g.N2, g.N3, g.full, g.L1y, g.L2y, g.inv_n, scale, rho);
     return hipGetLastError();
 }
 

@@ -164,9 +164,20 @@ def test_layout_defaults():
     assert (lay["L1x"], lay["L2x"]) == (8, 12)
     assert lay["plane_lds_bytes"] <= 160 * 1024
     assert lay["sticks_per_group"] * max(lay["L1z"], lay["L2z"]) <= 256
-    assert lay["plane_xmode"] == 1
+    # the whole plane fits (96 x 97 complex): x pass in place, 16 waves in FP64
+    assert lay["plane_xmode"] == 3 and lay["plane_lds_bytes"] == 96 * 97 * 16
+    assert lay["plane_threads"] == 1024
     pf = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, precision="f32")
-    assert pf.layout()["plane_lds_bytes"] < lay["plane_lds_bytes"]
+    assert pf.layout()["plane_lds_bytes"] == 96 * 97 * 8
+    p1 = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=1)
+    assert p1.layout()["plane_xmode"] == 1 and p1.layout()["plane_lds_bytes"] <= 160 * 1024
+    # 128^3 FP64: the whole plane (128 x 129 x 16 B) does not fit
+    p128 = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0)
+    assert p128.layout()["plane_xmode"] == 1
+    with pytest.raises(vloc.VlocError):
+        vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, plane_xmode=3)
+    assert vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0,
+                     precision="f32").layout()["plane_xmode"] == 3
     pq = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=2)
     assert pq.layout()["plane_xmode"] == 2 and pq.layout()["plane_lds_bytes"] == 49 * 97 * 16
     with pytest.raises(vloc.VlocError):

@@ -87,7 +87,10 @@ typedef struct {
                                  2 = occupied x-planes, one lane quad per x row
                                  (needs N1 in {24, 72, 80, 96} with the matching y
                                  split and N2 <= 128); 3 = the whole plane, x pass
-                                 in place (N1 (N2 + 1) elements <= 160 KiB)        */
+                                 in place over the workgroup (N1 (N2 + 1) elements
+                                 <= 160 KiB); 4 = as 3 with the x rows owned by
+                                 wavefronts (no workgroup barrier inside the x
+                                 pass)                                             */
     int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
                                  each axis (x, y, z); 0 = automatic (the most
                                  balanced split); else L1 and L / L1 must both be
@@ -156,7 +159,7 @@ vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
 /* Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
  * sticks_per_group, band_chunk}; out[8..13] = {plane_rows, plane_threads,
  * plane_lds_bytes, nxo, plane_xwaves, plane_xmode} where nxo is the number of
- * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads) or 3
+ * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads), 3 or 4
  * (whole plane). */
 vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14]);
 

@@ -192,7 +192,15 @@ vloc_status upload(Engine &E)
     {
         const Split *sp[3] = {&h.sx, &h.sy, &h.sz};
         for (int a = 0; a < 3; ++a) {
-            std::vector<double> t64 = twiddle_table(sp[a]->L);
+            // stage twiddles W_L^{n2 k1} arranged [n2][k1]
+            const std::vector<double> nat = twiddle_table(sp[a]->L);
+            std::vector<double> t64(nat.size());
+            for (int n2 = 0; n2 < sp[a]->L2; ++n2)
+                for (int k1 = 0; k1 < sp[a]->L1; ++k1) {
+                    const int j = n2 * k1, d = n2 * sp[a]->L1 + k1;
+                    t64[2 * d] = nat[2 * j];
+                    t64[2 * d + 1] = nat[2 * j + 1];
+                }
             if (h.opt.precision == VLOC_F32) {
                 std::vector<float> t32(t64.begin(), t64.end());
                 float *d = nullptr;
@@ -225,6 +233,7 @@ vloc_status upload(Engine &E)
         g.L1z = h.sz.L1;
         g.L2z = h.sz.L2;
         g.nxo = h.nxo;
+        g.nxo_magic = ((1ull << 40) + (unsigned)h.nxo - 1) / (unsigned)h.nxo;
         g.hmin_mod = ((h.hmin % g.N1) + g.N1) % g.N1;
         g.ldy = h.ldy;
         g.ldx = h.ldx;
@@ -238,7 +247,7 @@ vloc_status upload(Engine &E)
         g.zy = h.zy;
         g.zz = h.zz;
         g.fx = h.fx;
-        g.full = h.plane_full ? 1 : 0;
+        g.full = h.plane_full;
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E.device) !=
                 hipSuccess ||
@@ -765,7 +774,7 @@ vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14])
     int32_t v[14] = {h.sx.L1,      h.sx.L2,         h.sy.L1,      h.sy.L2, h.sz.L1,
                      h.sz.L2,      h.group_cap,     h.band_chunk, h.plane_rows,
                      h.plane_threads, h.plane_lds, h.nxo,        h.plane_xw,
-                     h.plane_full ? 3 : (h.plane_xq ? 2 : 1)};
+                     h.plane_full ? 2 + h.plane_full : (h.plane_xq ? 2 : 1)};
     std::memcpy(out, v, sizeof v);
     return VLOC_OK;
 }

@@ -94,13 +94,16 @@ __device__ __forceinline__ constexpr bool masked(int n1)
     return ZM != 0 && ((ZM >> n1) & 1);
 }
 
-// x[k1] *= W_L^{S n2 k1}; the table holds exp(-2 pi i j / L) and n2 k1 < L.
+// x[k1] *= W_L^{S n2 k1}, L = R L2; the table holds W_L^{n2 k1} =
+// exp(-2 pi i n2 k1 / L) at [n2][k1] (R entries per n2), so a task's
+// twiddles are one contiguous run.
 template <int R, int S, typename T>
 __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
 {
+    const cx<T> *w_n2 = tw + n2 * R;
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) {
-        cx<T> w = tw[n2 * k1];
+        cx<T> w = w_n2[k1];
         T wr = w.x, wi = (S < 0) ? w.y : -w.y;
         T a = xr[k1], b = xi[k1];
         xr[k1] = a * wr - b * wi;
@@ -527,6 +530,10 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     const int N2 = CY1 ? CY1 * CY2 : g.N2;
     const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
     const int nxo = g.nxo;
+    // task / nxo by a 64-bit multiply and shift (exact for tasks < 2^16)
+    auto div_nxo = [&](int v) {
+        return (int)(((unsigned long long)(unsigned)v * g.nxo_magic) >> 40);
+    };
     // row buffer length: L1x (L2x + 1) padded to L2x mod 16 (bank spread of
     // the stage-A writes across two rows); the host uses the same rule
     const int RB = g.rb;
@@ -655,7 +662,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L2y; task += nthr) {
-                const int n2 = task / nxo, hc = task - n2 * nxo;
+                const int n2 = div_nxo(task), hc = task - n2 * nxo;
                 const int2 ci = cols[hc];
                 cx<T> *col = plane + hc * ldy + n2;
                 T xr[R], xi[R];
@@ -663,9 +670,11 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                 for (int n1 = 0; n1 < R; ++n1) {
                     cx<T> v = mk<T>(T(0), T(0));
                     if (!masked<ZY>(n1)) {
+                        // in-plane read, then select: no divergent branch
                         int rel = n2 + L2y * n1 - ci.x;
                         if (rel < 0) rel += N2;
-                        if (rel < ci.y) v = col[L2y * n1];
+                        const cx<T> u = col[L2y * n1];
+                        if (rel < ci.y) v = u;
                     }
                     xr[n1] = v.x;
                     xi[n1] = v.y;
@@ -681,7 +690,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         with_size<CY2>(L2y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L1y; task += nthr) {
-                const int k1 = task / nxo, hc = task - k1 * nxo;
+                const int k1 = div_nxo(task), hc = task - k1 * nxo;
                 cx<T> *col = plane + hc * ldy + L2y * k1;
                 T xr[R], xi[R];
 #pragma unroll
@@ -881,7 +890,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     with_size<CY2>(L2y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L1y; task += nthr) {
-            const int k1 = task / nxo, hc = task - k1 * nxo;
+            const int k1 = div_nxo(task), hc = task - k1 * nxo;
             cx<T> *col = plane + hc * ldy + L2y * k1;
             T xr[R], xi[R];
 #pragma unroll
@@ -900,7 +909,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     with_size<CY1>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
-            const int n2 = task / nxo, hc = task - n2 * nxo;
+            const int n2 = div_nxo(task), hc = task - n2 * nxo;
             const int2 ci = cols[hc];
             cx<T> *col = plane + hc * ldy + n2;
             T xr[R], xi[R];
@@ -963,7 +972,8 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
 // other groups check occupancy per position.  Non-occupied positions of a row
 // may hold stale values: they are never read as input.  The potential comes
 // pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
-template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF>
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
+          bool WPR>
 __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
                                                 const Launch &L, cx<T> *__restrict__ S,
                                                 const T *__restrict__ VT,
@@ -978,6 +988,10 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     const int N2 = CY1 ? CY1 * CY2 : g.N2;
     const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
     const int nxo = g.nxo, hx = g.hmin_mod;
+    // task / nxo by a 64-bit multiply and shift (exact for tasks < 2^16)
+    auto div_nxo = [&](int v) {
+        return (int)(((unsigned long long)(unsigned)v * g.nxo_magic) >> 40);
+    };
     const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
     const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
     const int nb = L.nbt;
@@ -1100,7 +1114,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L2y; task += nthr) {
-                const int n2 = task / nxo, hc = task - n2 * nxo;
+                const int n2 = div_nxo(task), hc = task - n2 * nxo;
                 const int2 ci = cols[hc];
                 cx<T> *col = plane + col_of(hc) * ldy + n2;
                 T xr[R], xi[R];
@@ -1108,9 +1122,11 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 for (int n1 = 0; n1 < R; ++n1) {
                     cx<T> v = mk<T>(T(0), T(0));
                     if (!masked<ZY>(n1)) {
+                        // in-plane read, then select: no divergent branch
                         int rel = n2 + L2y * n1 - ci.x;
                         if (rel < 0) rel += N2;
-                        if (rel < ci.y) v = col[L2y * n1];
+                        const cx<T> u = col[L2y * n1];
+                        if (rel < ci.y) v = u;
                     }
                     xr[n1] = v.x;
                     xi[n1] = v.y;
@@ -1126,7 +1142,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         with_size<CY2>(L2y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L1y; task += nthr) {
-                const int k1 = task / nxo, hc = task - k1 * nxo;
+                const int k1 = div_nxo(task), hc = task - k1 * nxo;
                 cx<T> *col = plane + col_of(hc) * ldy + L2y * k1;
                 T xr[R], xi[R];
 #pragma unroll
@@ -1141,44 +1157,44 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             }
         });
         __syncthreads();
-        // x forward, stage A, in place: row yp, inputs x = n2 + L2x n1
-        with_size<CX1>(L1x, [&](auto RC) {
-            constexpr int R = decltype(RC)::value;
-            for (int task = tid; task < L2x * N2; task += nthr) {
-                const int n2 = task / N2, yp = task - n2 * N2;
-                cx<T> *row = plane + n2 * ldy + yp;
-                T xr[R], xi[R];
-#pragma unroll
-                for (int n1 = 0; n1 < R; ++n1) {
-                    cx<T> v = mk<T>(T(0), T(0));
-                    if (!masked<ZX>(n1)) {
-                        if (masked<FX>(n1) || occupied(n2 + L2x * n1)) v = row[L2x * n1 * ldy];
-                    }
-                    xr[n1] = v.x;
-                    xi[n1] = v.y;
-                }
-                Dft<R, -1, T>::run(xr, xi);
-                twiddle<R, -1, T>(xr, xi, n2, twx);
-#pragma unroll
-                for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
-            }
-        });
-        __syncthreads();
     }
 
-    // x stage B: frequencies x = k1 + L1x k2 of row yp, with the potential
-    // (APPLY), the density (DENSITY) or the real-space values (G2R / R2G)
-    with_size<CX2>(L2x, [&](auto RC) {
-        constexpr int R = decltype(RC)::value;
-        for (int task = tid; task < L1x * N2; task += nthr) {
-            const int k1 = task / N2, yp = task - k1 * N2;
+    // x pass.  stage_a: forward x stage A of row yp for n2 (inputs x = n2 + L2x n1);
+    // stage_b: stage B of row yp for k1 (frequencies x = k1 + L1x k2) with the
+    // potential, the density or the real-space values; stage_a2: reverse stage
+    // A', occupied outputs only.  All in place in P.
+    auto stage_a = [&](int n2, int yp) {
+        with_size<CX1>(L1x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            cx<T> *row = plane + n2 * ldy + yp;
+            T xr[R], xi[R];
+#pragma unroll
+            for (int n1 = 0; n1 < R; ++n1) {
+                cx<T> v = mk<T>(T(0), T(0));
+                if (!masked<ZX>(n1)) {
+                    const cx<T> u = row[L2x * n1 * ldy];
+                    if (masked<FX>(n1) || occupied(n2 + L2x * n1)) v = u;
+                }
+                xr[n1] = v.x;
+                xi[n1] = v.y;
+            }
+            Dft<R, -1, T>::run(xr, xi);
+            twiddle<R, -1, T>(xr, xi, n2, twx);
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
+        });
+    };
+    auto stage_b = [&](int k1, int yp) {
+        with_size<CX2>(L2x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + L2x * k1 * ldy + yp;
             T xr[R], xi[R];
             T vv[R];
             if (MODE == MODE_APPLY) {
-                const T *vcol = VTz + (long long)k1 * N2 + yp;
+                // the task's R values of the potential are contiguous
+                const T *vrun = VTz + ((long long)k1 * N2 + yp) * R;
 #pragma unroll
-                for (int k2 = 0; k2 < R; ++k2) vv[k2] = vcol[(long long)L1x * k2 * N2];
+                for (int k2 = 0; k2 < R; ++k2) vv[k2] = vrun[k2];
             }
             // natural row index of position yp (psi is [z][y][x])
             const int y = (yp % L2y) * L1y + yp / L2y;
@@ -1223,16 +1239,11 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
 #pragma unroll
                 for (int n2 = 0; n2 < R; ++n2) row[n2 * ldy] = mk<T>(xr[n2], xi[n2]);
             }
-        }
-    });
-    __syncthreads();
-    if (MODE == MODE_G2R || MODE == MODE_DENSITY) continue;
-
-    // x reverse, stage A': occupied outputs only
-    with_size<CX1>(L1x, [&](auto RC) {
-        constexpr int R = decltype(RC)::value;
-        for (int task = tid; task < L2x * N2; task += nthr) {
-            const int n2 = task / N2, yp = task - n2 * N2;
+        });
+    };
+    auto stage_a2 = [&](int n2, int yp) {
+        with_size<CX1>(L1x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + n2 * ldy + yp;
             T xr[R], xi[R];
 #pragma unroll
@@ -1249,14 +1260,50 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 if (masked<FX>(n1) || occupied(n2 + L2x * n1))
                     row[L2x * n1 * ldy] = mk<T>(xr[n1], xi[n1]);
             }
+        });
+    };
+    constexpr bool XPASS_ONLY_FWD = (MODE == MODE_G2R || MODE == MODE_DENSITY);
+    if constexpr (WPR) {
+        // each wavefront owns a block of rows (in yp order), in batches whose
+        // stage-A tasks fill at most one wavefront; only wavefront ordering
+        const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+        const int rpw = (N2 + nwaves - 1) / nwaves;
+        const int ybeg = min(N2, wave * rpw), yend = min(N2, ybeg + rpw);
+        const int rbx = L2x >= 64 ? 1 : 64 / L2x;
+        for (int y0 = ybeg; y0 < yend; y0 += rbx) {
+            const int nr = min(rbx, yend - y0);
+            if (MODE != MODE_R2G) {
+                for (int task = lane; task < nr * L2x; task += 64)
+                    stage_a(task / nr, y0 + task % nr);
+                wave_sync();
+            }
+            for (int task = lane; task < nr * L1x; task += 64) stage_b(task / nr, y0 + task % nr);
+            wave_sync();
+            if (!XPASS_ONLY_FWD) {
+                for (int task = lane; task < nr * L2x; task += 64)
+                    stage_a2(task / nr, y0 + task % nr);
+                wave_sync();
+            }
         }
-    });
-    __syncthreads();
+        __syncthreads();
+        if (XPASS_ONLY_FWD) continue;
+    } else {
+        // the three stages spread over the whole workgroup, lanes along yp
+        if (MODE != MODE_R2G) {
+            for (int task = tid; task < L2x * N2; task += nthr) stage_a(task / N2, task % N2);
+            __syncthreads();
+        }
+        for (int task = tid; task < L1x * N2; task += nthr) stage_b(task / N2, task % N2);
+        __syncthreads();
+        if (XPASS_ONLY_FWD) continue;
+        for (int task = tid; task < L2x * N2; task += nthr) stage_a2(task / N2, task % N2);
+        __syncthreads();
+    }
     // y reverse, stage B'
     with_size<CY2>(L2y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L1y; task += nthr) {
-            const int k1 = task / nxo, hc = task - k1 * nxo;
+            const int k1 = div_nxo(task), hc = task - k1 * nxo;
             cx<T> *col = plane + col_of(hc) * ldy + L2y * k1;
             T xr[R], xi[R];
 #pragma unroll
@@ -1275,7 +1322,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     with_size<CY1>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
-            const int n2 = task / nxo, hc = task - n2 * nxo;
+            const int n2 = div_nxo(task), hc = task - n2 * nxo;
             const int2 ci = cols[hc];
             cx<T> *col = plane + col_of(hc) * ldy + n2;
             T xr[R], xi[R];
@@ -1306,30 +1353,34 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
 }
 
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT>
+          int MAXT, bool WPR>
 __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, Launch L,
                                                      cx<T> *__restrict__ S,
                                                      const T *__restrict__ VT,
                                                      cx<T> *__restrict__ psi, long long band0)
 {
     // prefetched slots per thread cover 2048 slots
-    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT>(
+    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR>(
         g, t, L, S, VT, psi, band0);
 }
 
-// VT[z][x][yp] = V[z][y][x], yp = L2y (y mod L1y) + y / L1y: the potential in
-// the order the full-plane kernel reads it (contiguous along yp).
+// VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)
+// + y / L1y: the potential in the order the full-plane kernel's x stage B
+// reads it (each task's L2x values contiguous, tasks along yp adjacent).
 template <typename T>
 __global__ void k_arrange_v(const T *__restrict__ V, T *__restrict__ VT, int N1, int N2, int N3,
-                            int L1y, int L2y)
+                            int L1x, int L2x, int L1y, int L2y)
 {
     const long long n = (long long)N1 * N2 * N3;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const long long zx = i / N2;
-        const int yp = (int)(i - zx * N2);
-        const long long z = zx / N1;
-        const int x = (int)(zx - z * N1);
+        const long long r = i / L2x;
+        const int k2 = (int)(i - r * L2x);
+        const long long q = r / N2;
+        const int yp = (int)(r - q * N2);
+        const long long z = q / L1x;
+        const int k1 = (int)(q - z * L1x);
+        const int x = k1 + L1x * k2;
         const int y = (yp % L2y) * L1y + yp / L2y;
         VT[i] = V[(z * N2 + y) * N1 + x];
     }
@@ -1464,15 +1515,22 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
                            reinterpret_cast<cx<T> *>(psi), (long long)band0);
         return hipGetLastError();
     };
-    // more than 512 threads: compiled for FP64 application and density; the
-    // diagnostic transforms run the same body on 512 threads
-    if constexpr (std::is_same<T, double>::value && (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
-        if (threads > 768)
-            return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024>, threads);
-        if (threads > 512)
-            return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768>, threads);
-    }
-    return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512>, threads < 512 ? threads : 512);
+    auto pick = [&](auto wpr) {
+        constexpr bool W = decltype(wpr)::value;
+        // more than 512 threads: compiled for FP64 application and density; the
+        // diagnostic transforms run the same body on 512 threads
+        if constexpr (std::is_same<T, double>::value &&
+                      (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
+            if (threads > 768)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W>, threads);
+            if (threads > 512)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W>, threads);
+        }
+        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W>,
+                  threads < 512 ? threads : 512);
+    };
+    if (g.full == 2) return pick(std::true_type{});
+    return pick(std::false_type{});
 }
 
 // Specialised line splits for the common grids; any other split runs the same
@@ -1490,6 +1548,7 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const
             return launch_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY>(g, t, L, S, V, psi,      \
                                                                          band0, threads, lds, st);
         VLOC_FULL_CASE(8, 12, 8, 12, 0x38, 0xC3, 0x38)
+        VLOC_FULL_CASE(12, 8, 8, 12, 0x1F0, 0xE07, 0x38)
         VLOC_FULL_CASE(8, 9, 8, 12, 0x38, 0xC3, 0x3C)
         VLOC_FULL_CASE(8, 16, 8, 16, 0x38, 0xC3, 0x38)
         VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
@@ -1559,7 +1618,7 @@ hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStrea
     const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_arrange_v<T>, dim3(blocks), dim3(256), 0, st,
                        reinterpret_cast<const T *>(V), reinterpret_cast<T *>(VT), g.N1, g.N2,
-                       g.N3, g.L1y, g.L2y);
+                       g.N3, g.L1x, g.L2x, g.L1y, g.L2y);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ struct DevTables {
     const int4 *slot_info;  // per slot: {offset, count, lmin mod N3, plane position}
     const int2 *groups;     // per group: {first slot, number of sticks}
     const int2 *cols;       // per occupied x-plane: {first k mod N2, number of k}
-    const void *twx, *twy, *twz; // exp(-2 pi i j / L), complex of the plan precision
+    const void *twx, *twy, *twz; // exp(-2 pi i n2 k1 / L) at [n2][k1] (L = L1 L2, k1 < L1),
+                                 // complex of the plan precision
     const double2 *twx64;        // exp(-2 pi i j / N1) in FP64 (quad x pass)
     double *partial;             // density: [nsub][N3][N2][N1] partial sums (FP64)
     const double *wts;           // density: band weights (FP64)
@@ -26,6 +27,7 @@ struct Geometry {
     int N1, N2, N3;
     int L1x, L2x, L1y, L2y, L1z, L2z;
     int nxo;        // occupied x-planes
+    unsigned long long nxo_magic; // ceil(2^40 / nxo): v / nxo = (v nxo_magic) >> 40, v < 2^16
     int hmin_mod;   // hmin mod N1
     int ldy, ldx, ldz;
     int rows;       // unused (kept for layout reporting)
@@ -34,7 +36,8 @@ struct Geometry {
     int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
     int fx;         // x stage-A groups whose every position is occupied
-    int full;       // plane kernel holds the whole plane (x pass in place)
+    int full;       // plane kernel holds the whole plane, x pass in place: 1 = spread
+                    // over the workgroup, 2 = rows owned by wavefronts (0 = no)
     int resident_plane_wgs; // plane workgroups resident at once on the device
     int nsub;       // density: band subsets per launch
     int group_cap;  // most sticks in one group (over all segments)
@@ -92,8 +95,8 @@ template <typename T>
 hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const double *w,
                               const double *scale, double factor, void *y, hipStream_t st);
 
-// VT[z][x][yp] = V[z][y][x] with yp the row's position after the y pass (the
-// full-plane kernel's order of the potential).
+// VT[z][k1][yp][k2] = V[z][y][k1 + L1x k2] with yp the row's position after the
+// y pass (the full-plane kernel's order of the potential).
 template <typename T>
 hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStream_t st);
 // K3: stick z-transforms (r -> G direction) with 1/N, gathering into each

@@ -197,11 +197,11 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
         (p.opt.plane_threads > 512 && p.opt.precision != VLOC_F64) ||
         p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
-        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 3 || p.opt.gamma < 0 ||
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 4 || p.opt.gamma < 0 ||
         p.opt.gamma > 1) {
         err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64 "
               "(FP64: up to 1024), "
-              "plane_xwaves <= plane_threads / 64, plane_xmode 0..3, gamma 0..1)";
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..4, gamma 0..1)";
         return VLOC_E_INVALID;
     }
     p.gamma = p.opt.gamma != 0;
@@ -504,12 +504,12 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     {
         const int64_t full_bytes = (int64_t)grid[0] * p.ldy * es;
         const bool fits = full_bytes <= lds_max;
-        if (p.opt.plane_xmode == 3 && !fits) {
-            err = "the full plane does not fit in LDS (plane_xmode 3)";
+        if (p.opt.plane_xmode >= 3 && !fits) {
+            err = "the full plane does not fit in LDS (plane_xmode 3 or 4)";
             return VLOC_E_INVALID;
         }
-        if (fits && (p.opt.plane_xmode == 3 || p.opt.plane_xmode == 0)) {
-            p.plane_full = true;
+        if (fits && (p.opt.plane_xmode >= 3 || p.opt.plane_xmode == 0)) {
+            p.plane_full = p.opt.plane_xmode == 4 ? 2 : 1;
             p.plane_xq = 0;
             p.plane_xw = 0;
             p.plane_rb = 0;

@@ -37,7 +37,8 @@ struct HostPlan {
     int32_t lmin = 0, lmax = 0;
     int32_t zx = 0, zy = 0, zz = 0; // stage-A input groups that are zero on every line
     int32_t fx = 0;                 // x stage-A groups whose every position is occupied
-    bool plane_full = false;        // plane kernel holds the whole plane (x pass in place)
+    int32_t plane_full = 0;         // whole plane in LDS, x pass in place: 1 = spread
+                                    // over the workgroup, 2 = rows per wavefront
 
     // deal of sticks to groups; slots are numbered so that each group's
     // sticks are contiguous

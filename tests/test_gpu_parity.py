@@ -145,7 +145,8 @@ def test_determinism_and_chunk_invariance():
                dict(deal="snake", sticks_per_group=5), dict(plane_rows=5, plane_threads=128),
                dict(plane_threads=64), dict(sticks_per_group=64), dict(plane_threads=1024),
                dict(plane_threads=1024, plane_xwaves=16, plane_rows=2),
-               dict(plane_threads=768, plane_xwaves=12)):
+               dict(plane_threads=768, plane_xwaves=12), dict(plane_xmode=4),
+               dict(plane_xmode=4, plane_threads=256)):
         got = run(vloc.Plan(grid, cell, ecut, k, **kw), c, V)
         assert np.array_equal(got, base), kw
 
@@ -204,11 +205,11 @@ XMODE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("xmode", [1, 2, 3])
+@pytest.mark.parametrize("xmode", [1, 2, 3, 4])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("name,grid,cell,ecut,k,nb", XMODE_CASES)
 def test_plane_xmodes_vs_oracle(xmode, precision, name, grid, cell, ecut, k, nb):
-    """Row-buffer (1), lane-quad (2) and whole-plane (3) layouts of the plane kernel."""
+    """Row-buffer (1), lane-quad (2) and whole-plane (3, 4) layouts of the plane kernel."""
     label(test="xmode", xmode=xmode, precision=precision, name=name, grid=grid)
     hkl, c, V = case(grid, cell, ecut, k, nb)
     p = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_xmode=xmode)

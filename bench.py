@@ -264,7 +264,9 @@ def main():
         f"F_alg/band {sz['f_alg']:.3e} -> {flop_rate / 1e12:.1f} TFLOP/s; group PW max/min/mean "
         f"{bal.max()}/{bal.min()}/{bal.mean():.1f}")
     k2_launch_bytes = k2_bytes / kn[1] if kn[1] else None
-    traffic = read_traffic(args.precision, chunk)
+    # bands per launch: a call is cut into equal chunks of at most band_chunk
+    launch_bands = nb * args.steps / kn[1] if kn[1] else chunk
+    traffic = read_traffic(args.precision, launch_bands)
     result = {
         "metric": "band V_loc|psi> applications/sec at 96^3 (FP64 vs FP32) + % HBM peak",
         "value": round(bands_per_s, 1),
@@ -280,7 +282,8 @@ def main():
         "data": "synthetic (seeded Gaussian coefficients scaled by 1/(1+|G|^2); V = 0.5 + 32 Gaussians)",
         "config": {"workload": "96^3 grid, |G|<=24 sphere (57777 PW, 1793 sticks), 256 bands, Gamma, "
                                "cubic cell", "grid": list(r["grid"]), "nbands": nb,
-                   "npw": sz["npw"], "band_chunk": chunk, "precision": args.precision},
+                   "npw": sz["npw"], "band_chunk_max": chunk,
+                   "bands_per_launch": round(launch_bands, 2), "precision": args.precision},
         "hbm_frac_path": round(path_frac, 4),
         "roofline": {"bound": "hbm", "kernel": "k_plane (K2)",
                      "achieved": round(achieved / 1e9, 1) if achieved else None,
@@ -293,6 +296,9 @@ def main():
                                "k2_plane": round(kms[1] / args.steps, 4),
                                "k3_stick_bwd": round(kms[2] / args.steps, 4)},
     }
+    # FP64 band energies e_n = Re<c_n|V c_n> (FP64 reductions), kept to check FP32
+    e64 = r["plan"].band_dot(r["c"], r["out"]) if args.precision == "f64" else None
+    out64 = r["out"] if args.precision == "f64" else None
     del r
     torch.cuda.empty_cache()
     if args.copy_calibration:
@@ -309,8 +315,19 @@ def main():
         result["f32"] = {"value": round(v32, 1), "ms_per_step": round(r32["ms_total"] / args.steps, 4),
                          "speedup_vs_f64": round(v32 / bands_per_s, 3),
                          "hbm_frac_path": round(r32["sizes"]["b_alg"] * v32 / HBM_PEAK, 4)}
-        log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64)")
-        del r32
+        # accuracy of the FP32 path against the FP64 path (itself within 1e-12 of
+        # the oracle in the parity tests), every band of the workload; the FP32
+        # band energies use the FP64 reductions
+        o32 = r32["out"].to(torch.complex128)
+        rel = (torch.linalg.vector_norm(o32 - out64, dim=1) /
+               torch.linalg.vector_norm(out64, dim=1))
+        e32 = r32["plan"].band_dot(r32["c"], r32["out"])
+        erel = ((e32 - e64).abs() / e64.abs()).max().item()
+        result["f32"]["max_rel_err_per_band_vs_f64"] = float(f"{rel.max().item():.3e}")
+        result["f32"]["max_rel_err_band_energy_vs_f64"] = float(f"{erel:.3e}")
+        log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64); max per-band rel err "
+            f"{rel.max().item():.2e}, band-energy rel err {erel:.2e}")
+        del r32, o32
     if not args.no_gamma and args.precision == "f64":
         # the paper's real mode (Gamma point, half sphere, two bands per transform)
         # on the same grid and sphere: a different input class (real psi), so it

@@ -73,7 +73,9 @@ typedef struct {
     int32_t precision;        /* vloc_precision                                    */
     int32_t deal;             /* vloc_deal                                         */
     int32_t sticks_per_group; /* 0 = automatic; else 1..64                         */
-    int32_t band_chunk;       /* bands per internal chunk; 0 = automatic           */
+    int32_t band_chunk;       /* most bands (band pairs in the real mode) per launch;
+                                 a call is cut into equal chunks of at most this
+                                 many; 0 = automatic (stick buffer <= 256 MiB)     */
     int32_t plane_rows;       /* rows per x-pass batch of one wavefront in the plane
                                  kernel; 0 = automatic                             */
     int32_t plane_threads;    /* threads per plane workgroup (64..512, multiple of
@@ -222,9 +224,10 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
 typedef struct vloc_batch_s *vloc_batch; /* opaque; owned by the library */
 
 /* nk in [1, 8]; kpts: nk*3 doubles (reduced coordinates, as for a plan).
- * opt (NULL = defaults) applies to every member; its band_chunk counts bands
- * over all k-points per launch (0 = all bands in one launch).  Errors as for
- * vloc_plan_create_ex; on error *batch is NULL. */
+ * opt (NULL = defaults) applies to every member; its band_chunk is the most
+ * bands, counted over all k-points, of one launch (a call is cut into equal
+ * chunks; 0 = automatic: the chunk's stick buffers within 256 MiB).  Errors as
+ * for vloc_plan_create_ex; on error *batch is NULL. */
 vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const double cell[9],
                               double ecut, int32_t nk, const double *kpts,
                               const vloc_options *opt);

@@ -455,7 +455,11 @@ vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, cons
     std::vector<Launch> ls;
     const void *ins[1] = {mode == MODE_R2G ? nullptr : in};
     void *outs[1] = {(mode == MODE_APPLY || mode == MODE_R2G) ? out : nullptr};
-    size_t need = make_launches(E, ins, outs, &nbands, p->hp.band_chunk, ls);
+    // equal chunks of at most band_chunk launch bands (no short last chunk)
+    const int64_t units = p->hp.gamma ? (nbands + 1) / 2 : nbands;
+    const int64_t nch = (units + p->hp.band_chunk - 1) / p->hp.band_chunk;
+    const int64_t chunk = nch > 0 ? (units + nch - 1) / nch : 1;
+    size_t need = make_launches(E, ins, outs, &nbands, chunk, ls);
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
     void *psi = mode == MODE_G2R ? out : (mode == MODE_R2G ? const_cast<void *>(in) : nullptr);
     if (p->hp.opt.precision == VLOC_F32)
@@ -923,9 +927,19 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
     if (s != VLOC_OK) return s;
     int maxg = 1;
     for (vloc_plan p : batch->plans) maxg = std::max(maxg, p->hp.ngroups);
-    int64_t chunk = batch->band_chunk > 0 ? batch->band_chunk : total;
-    chunk = std::min<int64_t>(chunk, INT32_MAX / maxg);
-    chunk = std::min<int64_t>(chunk, INT32_MAX / h0.grid[2]);
+    // equal chunks of at most band_chunk bands (automatic: the members' stick
+    // buffers of one chunk within 256 MiB), each one launch per kernel
+    int64_t cmax = batch->band_chunk;
+    if (cmax <= 0) {
+        int64_t per_band = 0;
+        for (vloc_plan p : batch->plans)
+            per_band = std::max<int64_t>(per_band, (int64_t)h0.grid[2] * p->hp.nst() * es);
+        cmax = std::max<int64_t>(1, (256LL << 20) / per_band);
+    }
+    cmax = std::min<int64_t>(cmax, INT32_MAX / maxg);
+    cmax = std::min<int64_t>(cmax, INT32_MAX / h0.grid[2]);
+    const int64_t nch = (total + cmax - 1) / cmax;
+    const int64_t chunk = (total + nch - 1) / nch;
     std::vector<Launch> ls;
     size_t need = make_launches(E, c, out, nbands, chunk, ls);
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;

@@ -541,10 +541,12 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         }
     }
 
-    // ---- band chunk: stick buffer of one chunk <= 128 MiB (stays in the 256 MB
-    // memory-side cache between the three kernels)
+    // ---- band chunk: at most as many launch bands as keep the stick buffer
+    // within 256 MiB (measured at 96^3: larger chunks amortise the kernel
+    // boundaries; beyond this size nothing more is gained); a call's bands are
+    // then cut into equal chunks of at most this size
     int64_t per_band = (int64_t)Lz * nst * es;
-    int64_t chunk = std::max<int64_t>(1, (128LL << 20) / per_band);
+    int64_t chunk = std::max<int64_t>(1, (256LL << 20) / per_band);
     if (p.opt.band_chunk) chunk = p.opt.band_chunk;
     // stick-kernel blocks of one launch (chunk * ngroups) stay below 2^31
     chunk = std::min<int64_t>(chunk, INT32_MAX / std::max<int32_t>(1, p.ngroups));

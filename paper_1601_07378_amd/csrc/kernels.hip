@@ -992,8 +992,15 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     auto div_nxo = [&](int v) {
         return (int)(((unsigned long long)(unsigned)v * g.nxo_magic) >> 40);
     };
-    const cx<T> *twx = reinterpret_cast<const cx<T> *>(t.twx);
-    const cx<T> *twy = reinterpret_cast<const cx<T> *>(t.twy);
+    // LDS after the plane: the y and x stage twiddles and the occupied columns'
+    // k ranges, so that the transform stages issue no vector-memory loads other
+    // than the potential (a wait on one would also wait for the stick-buffer
+    // prefetch and stores still in flight)
+    cx<T> *twy = plane + N1 * ldy;
+    cx<T> *twx = twy + N2;
+    int2 *cols = reinterpret_cast<int2 *>(twx + N1);
+    for (int i = tid; i < N2; i += nthr) twy[i] = reinterpret_cast<const cx<T> *>(t.twy)[i];
+    for (int i = tid; i < N1; i += nthr) twx[i] = reinterpret_cast<const cx<T> *>(t.twx)[i];
     const int nb = L.nbt;
     // column of occupied x-plane hc
     auto col_of = [&](int hc) {
@@ -1055,6 +1062,8 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             const int sl = tid + i * nthr;
             spos[i] = sl < sg.nst ? sl_info[sl].w : 0;
         }
+        // the segment's column ranges into LDS (read after the next barrier)
+        for (int i = tid; i < nxo; i += nthr) cols[i] = t.cols[sg.col_off + i];
         spos_seg = si;
     };
 #pragma unroll
@@ -1089,7 +1098,6 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     const Seg sg = seg_at(L, si);
     const int nst = sg.nst;
     const int4 *slots = t.slot_info + sg.slot_off;
-    const int2 *cols = t.cols + sg.col_off;
     cx<T> *Sz = S + sg.s_off + ((long long)(bl - sg.band_lo) * g.N3 + z) * nst;
     if (si != spos_seg) load_pos(si);
     cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
@@ -1103,13 +1111,6 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
         for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
         __syncthreads();
-        {
-            int jn = jc, kn = kc, zz, bb;
-            if (advance(jn, kn)) {
-                plane_of(jn, kn, zz, bb);
-                prefetch(zz, bb);
-            }
-        }
         // y forward, stage A (lanes along occupied columns)
         with_size<CY1>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
@@ -1263,6 +1264,14 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         });
     };
     constexpr bool XPASS_ONLY_FWD = (MODE == MODE_G2R || MODE == MODE_DENSITY);
+    auto prefetch_next = [&]() {
+        if (MODE == MODE_R2G) return;
+        int jn = jc, kn = kc, zz, bb;
+        if (advance(jn, kn)) {
+            plane_of(jn, kn, zz, bb);
+            prefetch(zz, bb);
+        }
+    };
     if constexpr (WPR) {
         // each wavefront owns a block of rows (in yp order), in batches whose
         // stage-A tasks fill at most one wavefront; only wavefront ordering
@@ -1285,6 +1294,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 wave_sync();
             }
         }
+        prefetch_next();
         __syncthreads();
         if (XPASS_ONLY_FWD) continue;
     } else {
@@ -1294,6 +1304,9 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             __syncthreads();
         }
         for (int task = tid; task < L1x * N2; task += nthr) stage_b(task / N2, task % N2);
+        // the next plane's stick values: issued after the potential's loads, so
+        // their latency hides behind the reverse stages
+        prefetch_next();
         __syncthreads();
         if (XPASS_ONLY_FWD) continue;
         for (int task = tid; task < L2x * N2; task += nthr) stage_a2(task / N2, task % N2);

@@ -502,7 +502,9 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     // threads (no row buffers).  The default wherever it fits; the row-buffer
     // layout otherwise or when asked for.
     {
-        const int64_t full_bytes = (int64_t)grid[0] * p.ldy * es;
+        // the plane, then the y and x stage twiddles and the column k ranges
+        const int64_t full_bytes = (int64_t)grid[0] * p.ldy * es +
+                                   (int64_t)(grid[0] + grid[1]) * es + (int64_t)p.nxo * 8;
         const bool fits = full_bytes <= lds_max;
         if (p.opt.plane_xmode >= 3 && !fits) {
             err = "the full plane does not fit in LDS (plane_xmode 3 or 4)";

@@ -165,10 +165,12 @@ def test_layout_defaults():
     assert lay["plane_lds_bytes"] <= 160 * 1024
     assert lay["sticks_per_group"] * max(lay["L1z"], lay["L2z"]) <= 256
     # the whole plane fits (96 x 97 complex): x pass in place, 16 waves in FP64
-    assert lay["plane_xmode"] == 3 and lay["plane_lds_bytes"] == 96 * 97 * 16
+    # plane, then twiddles of both axes and the 49 columns' k ranges
+    assert lay["plane_xmode"] == 3
+    assert lay["plane_lds_bytes"] == 96 * 97 * 16 + (96 + 96) * 16 + 49 * 8
     assert lay["plane_threads"] == 1024
     pf = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, precision="f32")
-    assert pf.layout()["plane_lds_bytes"] == 96 * 97 * 8
+    assert pf.layout()["plane_lds_bytes"] == 96 * 97 * 8 + (96 + 96) * 8 + 49 * 8
     p1 = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=1)
     assert p1.layout()["plane_xmode"] == 1 and p1.layout()["plane_lds_bytes"] <= 160 * 1024
     # 128^3 FP64: the whole plane (128 x 129 x 16 B) does not fit

@@ -2,9 +2,11 @@
 //
 //   X[k] = sum_{n<R} x[n] exp(S 2 pi i n k / R),  S = -1 or +1,  R <= 16.
 //
-// Primes 2, 3, 5 and the radix 4 are written out from the definition; every
-// other size is split R = P*Q (P = 4 when 4 | R and R > 4, else the smallest
-// prime) by decimation in time with twiddles that are compile-time constants.
+// Primes 2, 3, 5 and the radix 4 are written out from the definition; sizes
+// with coprime factors (6, 10, 12, 15) use the prime-factor mapping (no
+// twiddles); 8, 9 and 16 are split R = P*Q (P = 4 when 4 | R and R > 4, else
+// the smallest prime) by decimation in time with twiddles that are
+// compile-time constants.
 // The constants come from a constexpr sine/cosine: exact integer reduction of
 // the angle numerator to the first half-quadrant, then a Taylor series.
 #pragma once
@@ -258,6 +260,61 @@ struct Dft {
         }
     }
 };
+
+// Prime-factor (Good-Thomas) split of R = A B with gcd(A, B) = 1: with the
+// input index n = (B n1 + A n2) mod R and the output index
+// k = (B (B^-1 mod A) k1 + A (A^-1 mod B) k2) mod R the DFT becomes an A x B
+// two-dimensional DFT with no twiddle factors.
+constexpr int inv_mod(int a, int m)
+{
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
+template <int A, int B, int S, typename T>
+struct Pfa {
+    static __host__ __device__ __forceinline__ void run(T *xr, T *xi)
+    {
+        constexpr int R = A * B;
+        constexpr int ka = B * inv_mod(B, A), kb = A * inv_mod(A, B);
+        T yr[A][B], yi[A][B];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) {
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) {
+                yr[n1][n2] = xr[(B * n1 + A * n2) % R];
+                yi[n1][n2] = xi[(B * n1 + A * n2) % R];
+            }
+            Dft<B, S, T>::run(yr[n1], yi[n1]);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            T zr[A], zi[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) {
+                zr[n1] = yr[n1][k2];
+                zi[n1] = yi[n1][k2];
+            }
+            Dft<A, S, T>::run(zr, zi);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) {
+                xr[(ka * k1 + kb * k2) % R] = zr[k1];
+                xi[(ka * k1 + kb * k2) % R] = zi[k1];
+            }
+        }
+    }
+};
+
+// Sizes with coprime factors use the prime-factor split.
+template <int S, typename T>
+struct Dft<6, S, T> : Pfa<2, 3, S, T> {};
+template <int S, typename T>
+struct Dft<10, S, T> : Pfa<2, 5, S, T> {};
+template <int S, typename T>
+struct Dft<12, S, T> : Pfa<4, 3, S, T> {};
+template <int S, typename T>
+struct Dft<15, S, T> : Pfa<3, 5, S, T> {};
 
 // Sizes a plan may use for the two factors of a line length.
 __host__ __device__ constexpr bool codelet_supported(int R)

@@ -195,6 +195,58 @@ def measure_batch(steps, warmup):
     return res
 
 
+def measure_grad(steps, warmup):
+    """The differentiable energy at 128^3, |G| <= 32 (137,065 PW), 512 bands:
+    one step = forward (apply, band energies, weighted sum) and backward
+    (dE/dc, dE/dV by the density pass, dE/dw), FP32 with FP64 reductions, and
+    the same in FP64."""
+    import torch
+
+    import synth
+    from paper_1601_07378_amd import autograd, vloc
+
+    w_ = synth.WORKLOADS["c5_128"]
+    grid, cell, ecut, nb = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"]), w_["nbands"]
+    res = {}
+    for prec in ("f32", "f64"):
+        ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
+            (torch.complex64, torch.float32)
+        plan = vloc.Plan(grid, cell, ecut, precision=prec)
+        c = torch.from_numpy(synth.coefficients(plan.gvectors(), nb)).to("cuda", ct)
+        V = torch.from_numpy(synth.potential(grid, w_["ngauss"])).to("cuda", rt)
+        w = torch.from_numpy(synth.band_weights(nb)).to("cuda", torch.float64)
+        c.requires_grad_(True)
+        V.requires_grad_(True)
+        w.requires_grad_(True)
+        stream = torch.cuda.current_stream()
+
+        def step():
+            c.grad = V.grad = w.grad = None
+            E = autograd.local_energy(plan, c, V, w)
+            E.backward()
+            return E
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = {"value": round(nb / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+                     "plane_xmode": plan.layout()["plane_xmode"]}
+        del c, V, w, plan
+        torch.cuda.empty_cache()
+    res["unit"] = "bands/s (energy + all gradients)"
+    res["workload"] = "128^3 grid, |G|<=32 sphere (137065 PW), 512 bands, Gamma, cubic cell"
+    res["speedup_f32_vs_f64"] = round(res["f32"]["value"] / res["f64"]["value"], 3)
+    return res
+
+
 def cpu_baseline(nbands_sample: int):
     import oracle
     import synth
@@ -225,6 +277,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-gamma", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of 256 MiB so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -351,6 +404,11 @@ def main():
         log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} bands/s, f64 batch "
             f"{rb['f64_batch']['value']:,.0f}, f64 plain {rb['f64_plain']['value']:,.0f} "
             f"({rb['schedule_source']})")
+    if not args.no_grad and args.precision == "f64":
+        rg = measure_grad(max(2, args.steps // 4), 1)
+        result["differentiable_energy"] = rg
+        log(f"# energy + gradients 128^3 x 512: f32 {rg['f32']['value']:,.0f} bands/s, "
+            f"f64 {rg['f64']['value']:,.0f} bands/s")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(args.cpu_sample)
         result["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()}

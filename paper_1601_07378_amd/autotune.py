@@ -46,9 +46,9 @@ def knob_space(grid, precision: str, batch: bool, total_bands: int) -> Dict[str,
         "split_y": [0] + axis_splits(grid[1]),
         "split_z": [0] + axis_splits(grid[2]),
         "sticks_per_group": [0, 8, 16, 24, 32, 48],
-        "plane_threads": [0, 256, 384],
+        "plane_threads": [0, 256, 384, 512] + ([768, 1024] if precision == "f64" else []),
         "plane_xwaves": [0, 2, 4],
-        "plane_xmode": [0, 2],
+        "plane_xmode": [0, 1, 2, 3, 4],
         "deal": ["greedy", "contiguous"],
         "band_chunk": chunks,
     }
@@ -146,6 +146,7 @@ class Tuner:
         if not self.batch:
             space.pop("band_chunk")
         best = {k: v[0] for k, v in space.items()}
+        self.measure(best)  # warm-up: clocks and caches, not a trial
         best_t = self.measure(best)
         self.trials.append(dict(cfg=dict(best), ms=best_t))
         self.log(f"# tune start {best_t:.4f} ms")

@@ -25,24 +25,26 @@ def test_axis_splits():
             assert L % a == 0 and (L // a) in at.CODELETS
 
 
-def test_every_single_knob_candidate_plans():
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_every_single_knob_candidate_plans(precision):
     """Each one-knob departure from the defaults is accepted by the planner
     (host work only), and the split knobs reach the plan's layout."""
     grid, cell, ecut = C4["grid"], synth.cubic_cell(), synth.ecut_for_radius(C4["R"])
-    space = at.knob_space(grid, "f32", True, sum(C4["nbands"]))
+    space = at.knob_space(grid, precision, True, sum(C4["nbands"]))
     base = {k: v[0] for k, v in space.items()}
     for knob, values in space.items():
         for v in values:
             cfg = dict(base)
             cfg[knob] = v
-            b = vloc.Batch(grid, cell, ecut, C4["kpts"], precision="f32", **at.to_options(cfg))
+            b = vloc.Batch(grid, cell, ecut, C4["kpts"], precision=precision,
+                           **at.to_options(cfg))
             lay = b.plans[0].layout()
             if knob == "split_x" and v:
                 assert (lay["L1x"], lay["L2x"]) == (v, grid[0] // v)
             if knob == "split_z" and v:
                 assert (lay["L1z"], lay["L2z"]) == (v, grid[2] // v)
             if knob == "plane_xmode" and v:
-                assert lay["plane_xmode"] == 2
+                assert lay["plane_xmode"] == v
             b.close()
 
 

@@ -122,6 +122,17 @@ __device__ __forceinline__ Seg seg_by_block(const Launch &L, int v)
         if (v >= L.seg[i].blk_lo) s = i;
     return L.seg[s];
 }
+// Block numbering of K3: consecutive workgroups go to the eight XCDs in turn,
+// so renumber them to give each XCD one contiguous range of (band, group)
+// items; the output cache lines shared by neighbouring groups (the ends of
+// their coefficient runs) then meet in one L2 instead of being written back
+// partially from two.  A bijection on [0, nblk) for any nblk.  (K1 keeps the
+// hardware order, measured faster for its S writes.)
+__device__ __forceinline__ int xcd_block(int nblk)
+{
+    const int b = blockIdx.x, x = b & 7, q = nblk >> 3, r = nblk & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
 __device__ __forceinline__ int seg_index_by_band(const Launch &L, int v)
 {
     int s = 0;
@@ -246,8 +257,9 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *lines = reinterpret_cast<cx<T> *>(smem_raw);
-    const Seg sg = seg_by_block(L, blockIdx.x);
-    const int rb = blockIdx.x - sg.blk_lo;
+    const int vb = xcd_block(L.nblk);
+    const Seg sg = seg_by_block(L, vb);
+    const int rb = vb - sg.blk_lo;
     const int bl = rb / sg.ngroups, gr = rb - bl * sg.ngroups;
     const int2 gi = t.groups[sg.group_off + gr];
     const int s0 = gi.x, ns = gi.y;

@@ -32,6 +32,7 @@ struct Engine {
     int2 *d_groups = nullptr;
     int2 *d_cols = nullptr;
     int4 *d_gam = nullptr;
+    int *d_yslot = nullptr;
     void *d_tw[3] = {nullptr, nullptr, nullptr};
     double2 *d_twx64 = nullptr;
     std::vector<int> slot_off, group_off, col_off;
@@ -97,6 +98,7 @@ void free_device(Engine &E)
     free_ptr(E.d_groups);
     free_ptr(E.d_cols);
     free_ptr(E.d_gam);
+    free_ptr(E.d_yslot);
     free_ptr(E.d_twx64);
     for (void *&t : E.d_tw) free_ptr(t);
     free_ptr(E.d_S);
@@ -139,6 +141,7 @@ vloc_status upload(Engine &E)
     // member tables, concatenated: slots and groups relative to the member
     std::vector<int4> slot, gam;
     std::vector<int2> groups, cols;
+    std::vector<int> yslot;
     E.slot_off.clear();
     E.group_off.clear();
     E.col_off.clear();
@@ -180,11 +183,23 @@ vloc_status upload(Engine &E)
             }
         }
         for (int c = 0; c < m->nxo; ++c) cols.push_back(make_int2(m->col_kmin[c], m->col_kcnt[c]));
+        if (h.plane_full) {
+            // slot of each (occupied x-plane, row) position, -1 where no stick
+            const size_t y0 = yslot.size();
+            yslot.resize(y0 + (size_t)m->nxo * m->grid[1], -1);
+            for (int64_t s = 0; s < m->nst(); ++s) {
+                const Stick &st = m->sticks[m->stick_of_slot[s]];
+                int kp = st.k % m->grid[1];
+                if (kp < 0) kp += m->grid[1];
+                yslot[y0 + (size_t)(st.h - m->hmin) * m->grid[1] + kp] = (int)s;
+            }
+        }
     }
     if ((e = upload_vec(E.d_slot, slot)) != hipSuccess) goto devfail;
     if ((e = upload_vec(E.d_groups, groups)) != hipSuccess) goto devfail;
     if ((e = upload_vec(E.d_cols, cols)) != hipSuccess) goto devfail;
     if (!gam.empty() && (e = upload_vec(E.d_gam, gam)) != hipSuccess) goto devfail;
+    if (!yslot.empty() && (e = upload_vec(E.d_yslot, yslot)) != hipSuccess) goto devfail;
     if (h.plane_full) {
         const size_t vbytes = (size_t)h.grid[0] * h.grid[1] * h.grid[2] * (h.elem_bytes() / 2);
         if ((e = hipMalloc(&E.d_VT, vbytes)) != hipSuccess) goto devfail;
@@ -311,6 +326,7 @@ DevTables tables(const Engine &E)
     t.partial = E.d_partial;
     t.wts = nullptr;
     t.gam = E.d_gam;
+    t.yslot = E.d_yslot;
     return t;
 }
 

@@ -985,7 +985,7 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
 // may hold stale values: they are never read as input.  The potential comes
 // pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
-          bool WPR>
+          bool WPR, bool DYT>
 __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
                                                 const Launch &L, cx<T> *__restrict__ S,
                                                 const T *__restrict__ VT,
@@ -1063,31 +1063,63 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         }
     };
     auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
-    int spos[PF];
-    cx<T> sval[PF];
+    // Direct y stage A (wide FP64 workgroups, launches of one segment, at most
+    // one y task per thread): the forward pass takes its stage-A inputs straight
+    // from the prefetched stick values and the reverse pass stores its stage-A'
+    // outputs straight to S, so the plane needs no scatter and no gather.  The
+    // thread's task (yhc, yn2) and the slots of its positions stay the same for
+    // every plane.
+    constexpr bool DYC = DYT && CY1 > 0 && (MODE == MODE_APPLY || MODE == MODE_DENSITY);
+    constexpr int RY = CY1 > 0 ? CY1 : 1;
+    const bool dy = DYC && L.nseg == 1 && nxo * L2y <= nthr;
+    const bool ymine = tid < nxo * L2y;
+    const int yn2 = div_nxo(tid), yhc = tid - yn2 * nxo;
+    // Prefetch registers, shared by the two forms: plane positions and values
+    // of the slots tid + i nthr (scatter form), or slots and values of the
+    // thread's y-task positions (direct form)
+    constexpr int NP = PF > RY ? PF : RY;
+    int pos[NP];
+    cx<T> pre[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        pos[i] = -1;
+        pre[i] = mk<T>(T(0), T(0));
+    }
     int spos_seg = -1;
     auto load_pos = [&](int si) {
         const Seg sg = seg_at(L, si);
         const int4 *sl_info = t.slot_info + sg.slot_off;
+        if (DYC && dy) {
+            const int *ys = t.yslot + (long long)(sg.col_off + yhc) * N2 + yn2;
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int sl = tid + i * nthr;
-            spos[i] = sl < sg.nst ? sl_info[sl].w : 0;
+            for (int n1 = 0; n1 < RY; ++n1)
+                pos[n1] = (ymine && !masked<ZY>(n1)) ? ys[L2y * n1] : -1;
+        } else {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                const int sl = tid + i * nthr;
+                pos[i] = sl < sg.nst ? sl_info[sl].w : 0;
+            }
         }
         // the segment's column ranges into LDS (read after the next barrier)
         for (int i = tid; i < nxo; i += nthr) cols[i] = t.cols[sg.col_off + i];
         spos_seg = si;
     };
-#pragma unroll
-    for (int i = 0; i < PF; ++i) sval[i] = mk<T>(T(0), T(0));
     load_pos(0);
+    __syncthreads(); // twiddles and column ranges in LDS
     auto prefetch = [&](int zz, int bb) {
         const Seg sg = seg_at(L, seg_of(bb));
         const cx<T> *Sj = S + sg.s_off + ((long long)(bb - sg.band_lo) * g.N3 + zz) * sg.nst;
+        if (DYC && dy) {
+#pragma unroll
+            for (int n1 = 0; n1 < RY; ++n1)
+                if (!masked<ZY>(n1)) pre[n1] = pos[n1] >= 0 ? Sj[pos[n1]] : mk<T>(T(0), T(0));
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int sl = tid + i * nthr;
-            if (sl < sg.nst) sval[i] = Sj[sl];
+            if (sl < sg.nst) pre[i] = Sj[sl];
         }
     };
     int jc = j0, kc = 0;
@@ -1118,38 +1150,56 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     double *accz = DENS ? t.partial + ((long long)(bl / bps) * g.N3 + z) * N1 * N2 : nullptr;
 
     if (MODE != MODE_R2G) {
+        if (DYC && dy) {
+            // y forward, stage A, from the prefetched stick values (zero where no
+            // stick); the thread's positions are the ones it read back last plane
+            if (ymine) {
+                cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+                T xr[RY], xi[RY];
 #pragma unroll
-        for (int i = 0; i < PF; ++i)
-            if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
-        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
-        __syncthreads();
-        // y forward, stage A (lanes along occupied columns)
-        with_size<CY1>(L1y, [&](auto RC) {
-            constexpr int R = decltype(RC)::value;
-            for (int task = tid; task < nxo * L2y; task += nthr) {
-                const int n2 = div_nxo(task), hc = task - n2 * nxo;
-                const int2 ci = cols[hc];
-                cx<T> *col = plane + col_of(hc) * ldy + n2;
-                T xr[R], xi[R];
-#pragma unroll
-                for (int n1 = 0; n1 < R; ++n1) {
-                    cx<T> v = mk<T>(T(0), T(0));
-                    if (!masked<ZY>(n1)) {
-                        // in-plane read, then select: no divergent branch
-                        int rel = n2 + L2y * n1 - ci.x;
-                        if (rel < 0) rel += N2;
-                        const cx<T> u = col[L2y * n1];
-                        if (rel < ci.y) v = u;
-                    }
-                    xr[n1] = v.x;
-                    xi[n1] = v.y;
+                for (int n1 = 0; n1 < RY; ++n1) {
+                    xr[n1] = pre[n1].x;
+                    xi[n1] = pre[n1].y;
                 }
-                Dft<R, -1, T>::run(xr, xi);
-                twiddle<R, -1, T>(xr, xi, n2, twy);
+                Dft<RY, -1, T>::run(xr, xi);
+                twiddle<RY, -1, T>(xr, xi, yn2, twy);
 #pragma unroll
-                for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
+                for (int k1 = 0; k1 < RY; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
             }
-        });
+        } else {
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+                if (tid + i * nthr < nst) plane[pos[i]] = pre[i];
+            for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
+            __syncthreads();
+            // y forward, stage A (lanes along occupied columns)
+            with_size<CY1>(L1y, [&](auto RC) {
+                constexpr int R = decltype(RC)::value;
+                for (int task = tid; task < nxo * L2y; task += nthr) {
+                    const int n2 = div_nxo(task), hc = task - n2 * nxo;
+                    const int2 ci = cols[hc];
+                    cx<T> *col = plane + col_of(hc) * ldy + n2;
+                    T xr[R], xi[R];
+#pragma unroll
+                    for (int n1 = 0; n1 < R; ++n1) {
+                        cx<T> v = mk<T>(T(0), T(0));
+                        if (!masked<ZY>(n1)) {
+                            // in-plane read, then select: no divergent branch
+                            int rel = n2 + L2y * n1 - ci.x;
+                            if (rel < 0) rel += N2;
+                            const cx<T> u = col[L2y * n1];
+                            if (rel < ci.y) v = u;
+                        }
+                        xr[n1] = v.x;
+                        xi[n1] = v.y;
+                    }
+                    Dft<R, -1, T>::run(xr, xi);
+                    twiddle<R, -1, T>(xr, xi, n2, twy);
+#pragma unroll
+                    for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
+                }
+            });
+        }
         __syncthreads();
         // y forward, stage B
         with_size<CY2>(L2y, [&](auto RC) {
@@ -1343,6 +1393,28 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         }
     });
     __syncthreads();
+    if (DYC && dy) {
+        // y reverse, stage A', stick positions stored straight to S; the next
+        // plane's stage A writes only this thread's positions, so no barrier
+        if (ymine) {
+            cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+            T xr[RY], xi[RY];
+#pragma unroll
+            for (int k1 = 0; k1 < RY; ++k1) {
+                cx<T> v = col[L2y * k1];
+                xr[k1] = v.x;
+                xi[k1] = v.y;
+            }
+            twiddle<RY, +1, T>(xr, xi, yn2, twy);
+            Dft<RY, +1, T>::run(xr, xi);
+#pragma unroll
+            for (int n1 = 0; n1 < RY; ++n1) {
+                if (masked<ZY>(n1)) continue;
+                if (pos[n1] >= 0) Sz[pos[n1]] = mk<T>(xr[n1], xi[n1]);
+            }
+        }
+        continue;
+    }
     // y reverse, stage A': only stick positions are kept
     with_size<CY1>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
@@ -1371,7 +1443,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PF; ++i)
-        if (tid + i * nthr < nst) Sz[tid + i * nthr] = plane[spos[i]];
+        if (tid + i * nthr < nst) Sz[tid + i * nthr] = plane[pos[i]];
     for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = plane[slots[sl].w];
     __syncthreads(); // the next plane's scatter overwrites P
     }
@@ -1385,8 +1457,8 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
                                                      cx<T> *__restrict__ psi, long long band0)
 {
     // prefetched slots per thread cover 2048 slots
-    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR>(
-        g, t, L, S, VT, psi, band0);
+    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR,
+                    (MAXT >= 768)>(g, t, L, S, VT, psi, band0);
 }
 
 // VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)

@@ -21,6 +21,9 @@ struct DevTables {
     // (0 = stick of the half sphere, 1 = its mirror, 2 = the (0, 0) stick),
     // -lmin of the (0, 0) stick, index in the group of the mirror stick}
     const int4 *gam;
+    // whole-plane layout, per occupied x-plane hc and row y (hc-major, N2 per
+    // hc): the slot of stick (hmin + hc, y), or -1
+    const int *yslot;
 };
 
 struct Geometry {

@@ -985,7 +985,7 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
 // may hold stale values: they are never read as input.  The potential comes
 // pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
-          bool WPR, bool DYT>
+          bool WPR, int YT>
 __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
                                                 const Launch &L, cx<T> *__restrict__ S,
                                                 const T *__restrict__ VT,
@@ -1063,21 +1063,29 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         }
     };
     auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
-    // Direct y stage A (wide FP64 workgroups, launches of one segment, at most
-    // one y task per thread): the forward pass takes its stage-A inputs straight
-    // from the prefetched stick values and the reverse pass stores its stage-A'
-    // outputs straight to S, so the plane needs no scatter and no gather.  The
-    // thread's task (yhc, yn2) and the slots of its positions stay the same for
-    // every plane.
-    constexpr bool DYC = DYT && CY1 > 0 && (MODE == MODE_APPLY || MODE == MODE_DENSITY);
+    // Direct y stage A (launches of one segment, at most YT y tasks per
+    // thread): the forward pass takes its stage-A inputs straight from the
+    // prefetched stick values and the reverse pass stores its stage-A' outputs
+    // straight to S, so the plane needs no scatter and no gather.  A thread's
+    // tasks (yhc, yn2) = tid + u nthr and the slots of their positions stay the
+    // same for every plane.
+    constexpr bool DYC = YT > 0 && CY1 > 0 && (MODE == MODE_APPLY || MODE == MODE_DENSITY);
     constexpr int RY = CY1 > 0 ? CY1 : 1;
-    const bool dy = DYC && L.nseg == 1 && nxo * L2y <= nthr;
-    const bool ymine = tid < nxo * L2y;
-    const int yn2 = div_nxo(tid), yhc = tid - yn2 * nxo;
+    constexpr int NU = YT > 0 ? YT : 1;
+    const bool dy = DYC && L.nseg == 1 && nxo * L2y <= NU * nthr;
+    bool ymine[NU];
+    int yn2[NU], yhc[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int task = tid + u * nthr;
+        ymine[u] = task < nxo * L2y;
+        yn2[u] = div_nxo(task);
+        yhc[u] = task - yn2[u] * nxo;
+    }
     // Prefetch registers, shared by the two forms: plane positions and values
     // of the slots tid + i nthr (scatter form), or slots and values of the
     // thread's y-task positions (direct form)
-    constexpr int NP = PF > RY ? PF : RY;
+    constexpr int NP = PF > NU * RY ? PF : NU * RY;
     int pos[NP];
     cx<T> pre[NP];
 #pragma unroll
@@ -1090,10 +1098,13 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         const Seg sg = seg_at(L, si);
         const int4 *sl_info = t.slot_info + sg.slot_off;
         if (DYC && dy) {
-            const int *ys = t.yslot + (long long)(sg.col_off + yhc) * N2 + yn2;
 #pragma unroll
-            for (int n1 = 0; n1 < RY; ++n1)
-                pos[n1] = (ymine && !masked<ZY>(n1)) ? ys[L2y * n1] : -1;
+            for (int u = 0; u < NU; ++u) {
+                const int *ys = t.yslot + (long long)(sg.col_off + yhc[u]) * N2 + yn2[u];
+#pragma unroll
+                for (int n1 = 0; n1 < RY; ++n1)
+                    pos[u * RY + n1] = (ymine[u] && !masked<ZY>(n1)) ? ys[L2y * n1] : -1;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
@@ -1112,8 +1123,9 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         const cx<T> *Sj = S + sg.s_off + ((long long)(bb - sg.band_lo) * g.N3 + zz) * sg.nst;
         if (DYC && dy) {
 #pragma unroll
-            for (int n1 = 0; n1 < RY; ++n1)
-                if (!masked<ZY>(n1)) pre[n1] = pos[n1] >= 0 ? Sj[pos[n1]] : mk<T>(T(0), T(0));
+            for (int i = 0; i < NU * RY; ++i)
+                if (!masked<ZY>(i % RY))
+                    pre[i] = pos[i] >= 0 ? Sj[pos[i]] : mk<T>(T(0), T(0));
             return;
         }
 #pragma unroll
@@ -1153,16 +1165,18 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         if (DYC && dy) {
             // y forward, stage A, from the prefetched stick values (zero where no
             // stick); the thread's positions are the ones it read back last plane
-            if (ymine) {
-                cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                if (!ymine[u]) continue;
+                cx<T> *col = plane + col_of(yhc[u]) * ldy + yn2[u];
                 T xr[RY], xi[RY];
 #pragma unroll
                 for (int n1 = 0; n1 < RY; ++n1) {
-                    xr[n1] = pre[n1].x;
-                    xi[n1] = pre[n1].y;
+                    xr[n1] = pre[u * RY + n1].x;
+                    xi[n1] = pre[u * RY + n1].y;
                 }
                 Dft<RY, -1, T>::run(xr, xi);
-                twiddle<RY, -1, T>(xr, xi, yn2, twy);
+                twiddle<RY, -1, T>(xr, xi, yn2[u], twy);
 #pragma unroll
                 for (int k1 = 0; k1 < RY; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
             }
@@ -1396,8 +1410,10 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     if (DYC && dy) {
         // y reverse, stage A', stick positions stored straight to S; the next
         // plane's stage A writes only this thread's positions, so no barrier
-        if (ymine) {
-            cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            if (!ymine[u]) continue;
+            cx<T> *col = plane + col_of(yhc[u]) * ldy + yn2[u];
             T xr[RY], xi[RY];
 #pragma unroll
             for (int k1 = 0; k1 < RY; ++k1) {
@@ -1405,12 +1421,12 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle<RY, +1, T>(xr, xi, yn2, twy);
+            twiddle<RY, +1, T>(xr, xi, yn2[u], twy);
             Dft<RY, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < RY; ++n1) {
                 if (masked<ZY>(n1)) continue;
-                if (pos[n1] >= 0) Sz[pos[n1]] = mk<T>(xr[n1], xi[n1]);
+                if (pos[u * RY + n1] >= 0) Sz[pos[u * RY + n1]] = mk<T>(xr[n1], xi[n1]);
             }
         }
         continue;
@@ -1458,7 +1474,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
 {
     // prefetched slots per thread cover 2048 slots
     plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR,
-                    (MAXT >= 768)>(g, t, L, S, VT, psi, band0);
+                    (MAXT >= 768 ? 1 : 2)>(g, t, L, S, VT, psi, band0);
 }
 
 // VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)

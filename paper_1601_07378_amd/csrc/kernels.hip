@@ -1085,7 +1085,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     // Prefetch registers, shared by the two forms: plane positions and values
     // of the slots tid + i nthr (scatter form), or slots and values of the
     // thread's y-task positions (direct form)
-    constexpr int NP = PF > NU * RY ? PF : NU * RY;
+    constexpr int NP = (DYC && NU * RY > PF) ? NU * RY : PF;
     int pos[NP];
     cx<T> pre[NP];
 #pragma unroll
@@ -1465,16 +1465,19 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     }
 }
 
+// YT > 0: the direct y form with up to YT y tasks per thread (chosen by the
+// launcher when the geometry allows it; a separate instantiation, so that the
+// scatter form does not carry its registers)
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT, bool WPR>
+          int MAXT, bool WPR, int YT>
 __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, Launch L,
                                                      cx<T> *__restrict__ S,
                                                      const T *__restrict__ VT,
                                                      cx<T> *__restrict__ psi, long long band0)
 {
     // prefetched slots per thread cover 2048 slots
-    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR,
-                    (MAXT >= 768 ? 1 : 2)>(g, t, L, S, VT, psi, band0);
+    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR, YT>(
+        g, t, L, S, VT, psi, band0);
 }
 
 // VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)
@@ -1628,19 +1631,38 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
                            reinterpret_cast<cx<T> *>(psi), (long long)band0);
         return hipGetLastError();
     };
+    // direct y form: one segment, a specialised y split, apply (and FP32
+    // density; the FP64 density kernel would spill with it)
+    constexpr bool DYK = Y1 > 0 && (MODE == MODE_APPLY ||
+                                    (MODE == MODE_DENSITY && std::is_same<T, float>::value));
+    const bool dyok = DYK && L.nseg == 1;
     auto pick = [&](auto wpr) {
         constexpr bool W = decltype(wpr)::value;
         // more than 512 threads: compiled for FP64 application and density; the
         // diagnostic transforms run the same body on 512 threads
         if constexpr (std::is_same<T, double>::value &&
                       (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
-            if (threads > 768)
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W>, threads);
-            if (threads > 512)
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W>, threads);
+            const bool dy1 = !W && dyok && g.nxo * g.L2y <= threads;
+            if (threads > 768) {
+                if constexpr (DYK && !W)
+                    if (dy1)
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1>,
+                                  threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0>, threads);
+            }
+            if (threads > 512) {
+                if constexpr (DYK && !W)
+                    if (dy1)
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 1>,
+                                  threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 0>, threads);
+            }
         }
-        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W>,
-                  threads < 512 ? threads : 512);
+        const int nt = threads < 512 ? threads : 512;
+        if constexpr (DYK && !W && std::is_same<T, float>::value)
+            if (dyok && g.nxo * g.L2y <= 2 * nt)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2>, nt);
+        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0>, nt);
     };
     if (g.full == 2) return pick(std::true_type{});
     return pick(std::false_type{});

@@ -261,7 +261,7 @@ def cpu_baseline(nbands_sample: int):
     oracle.apply(grid, cell, ecut, (0, 0, 0), c, V, nthreads=threads)
     dt = time.perf_counter() - t0
     return dict(value=nbands_sample / dt, unit="bands/s", cores=threads, kind="oracle",
-                sample=f"first {nbands_sample} of the 256 bands of the 96^3/R=24 workload, "
+                sample=f"{nbands_sample} of the 256 bands of the 96^3/R=24 workload, "
                        f"FP64, full-cube unpruned FFTs, OpenMP over bands; {dt:.1f} s")
 
 
@@ -272,7 +272,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")

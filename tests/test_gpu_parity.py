@@ -247,3 +247,37 @@ def test_radix_splits_vs_oracle(split, precision):
     err = relerr_per_band(got, ref)
     print("split", split, precision, "err", err.max())
     assert err.max() <= tol
+
+
+# ------------------------------------------- direct and scatter forms of the y pass
+
+@pytest.mark.parametrize("precision,direct,scatter", [("f64", 1024, 512), ("f32", 512, 256)])
+def test_direct_y_form_equals_scatter_form(precision, direct, scatter):
+    """The plane kernel takes the y stage-A inputs straight from the prefetched
+    stick values (and stores stage A' straight to S) when every thread has at
+    most one y task (1024/768-thread FP64 workgroups) or two (512-thread FP32
+    ones): at 96^3 that is 49 columns x 12 = 588 tasks.  With `scatter` threads
+    the same plan runs the scatter/gather form.  The arithmetic is the same, so
+    outputs and densities agree bit for bit; both match the oracle."""
+    grid, cell, ecut, k, nb = (96, 96, 96), synth.cubic_cell(), 288.0, (0, 0, 0), 3
+    label(test="direct_y", precision=precision)
+    hkl, c, V = case(grid, cell, ecut, k, nb)
+    pd = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=direct)
+    ps = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=scatter)
+    assert pd.layout()["plane_xmode"] == ps.layout()["plane_xmode"] == 3
+    got_d, got_s = run(pd, c, V), run(ps, c, V)
+    assert np.array_equal(got_d, got_s)
+    if precision == "f64":
+        ref, tol = oracle.apply(grid, cell, ecut, k, c, V), TOL64
+    else:
+        ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                           V.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    assert relerr_per_band(got_d, ref).max() <= tol
+    # the density pass (direct form in FP32 only) against the scatter form
+    ct = torch.complex128 if precision == "f64" else torch.complex64
+    tc = torch.from_numpy(c).to("cuda", ct)
+    w = torch.from_numpy(synth.band_weights(nb)).cuda()
+    rd, rs = pd.density(tc, w), ps.density(tc, w)
+    torch.cuda.synchronize()
+    assert torch.equal(rd, rs)

@@ -111,6 +111,42 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
     }
 }
 
+// The same for twiddles held in LDS by the whole-plane kernel.  For an 8-point
+// first stage in FP64 only w^1, w^2 and w^4 are read; w^3, w^5, w^6 and w^7 are
+// their products (one or two roundings from the tabulated values): four complex
+// multiplies instead of four 16-byte LDS reads, for a kernel whose LDS traffic
+// is as long as its arithmetic.
+template <int R, int S, typename T>
+__device__ __forceinline__ void twiddle_lds(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
+{
+#ifndef VLOC_TW_READ_ALL
+    if constexpr (R == 8 && std::is_same<T, double>::value) {
+        const cx<T> *w_n2 = tw + n2 * R;
+        const cx<T> a = w_n2[1], b = w_n2[2], d = w_n2[4];
+        auto mul = [](cx<T> u, cx<T> v) {
+            return mk<T>(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
+        };
+        cx<T> w[R];
+        w[1] = a;
+        w[2] = b;
+        w[3] = mul(a, b);
+        w[4] = d;
+        w[5] = mul(a, d);
+        w[6] = mul(b, d);
+        w[7] = mul(w[3], d);
+#pragma unroll
+        for (int k1 = 1; k1 < R; ++k1) {
+            T wr = w[k1].x, wi = (S < 0) ? w[k1].y : -w[k1].y;
+            T u = xr[k1], v = xi[k1];
+            xr[k1] = u * wr - v * wi;
+            xi[k1] = u * wi + v * wr;
+        }
+        return;
+    }
+#endif
+    twiddle<R, S, T>(xr, xi, n2, tw);
+}
+
 // Segment of a launch by a uniform key (stick-kernel block or launch band):
 // the last segment whose first key is <= v.  The descriptor is read from the
 // kernel-argument segment with a uniform index (scalar loads), not held in
@@ -1176,7 +1212,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                     xi[n1] = pre[u * RY + n1].y;
                 }
                 Dft<RY, -1, T>::run(xr, xi);
-                twiddle<RY, -1, T>(xr, xi, yn2[u], twy);
+                twiddle_lds<RY, -1, T>(xr, xi, yn2[u], twy);
 #pragma unroll
                 for (int k1 = 0; k1 < RY; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
             }
@@ -1208,7 +1244,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                         xi[n1] = v.y;
                     }
                     Dft<R, -1, T>::run(xr, xi);
-                    twiddle<R, -1, T>(xr, xi, n2, twy);
+                    twiddle_lds<R, -1, T>(xr, xi, n2, twy);
 #pragma unroll
                     for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
                 }
@@ -1256,7 +1292,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xi[n1] = v.y;
             }
             Dft<R, -1, T>::run(xr, xi);
-            twiddle<R, -1, T>(xr, xi, n2, twx);
+            twiddle_lds<R, -1, T>(xr, xi, n2, twx);
 #pragma unroll
             for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
         });
@@ -1329,7 +1365,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle<R, +1, T>(xr, xi, n2, twx);
+            twiddle_lds<R, +1, T>(xr, xi, n2, twx);
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
@@ -1421,7 +1457,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle<RY, +1, T>(xr, xi, yn2[u], twy);
+            twiddle_lds<RY, +1, T>(xr, xi, yn2[u], twy);
             Dft<RY, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < RY; ++n1) {
@@ -1445,7 +1481,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle<R, +1, T>(xr, xi, n2, twy);
+            twiddle_lds<R, +1, T>(xr, xi, n2, twy);
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {

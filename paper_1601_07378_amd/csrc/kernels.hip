@@ -119,7 +119,6 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 template <int R, int S, typename T>
 __device__ __forceinline__ void twiddle_lds(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
 {
-#ifndef VLOC_TW_READ_ALL
     if constexpr (R == 8 && std::is_same<T, double>::value) {
         const cx<T> *w_n2 = tw + n2 * R;
         const cx<T> a = w_n2[1], b = w_n2[2], d = w_n2[4];
@@ -143,7 +142,6 @@ __device__ __forceinline__ void twiddle_lds(T *xr, T *xi, int n2, const cx<T> *_
         }
         return;
     }
-#endif
     twiddle<R, S, T>(xr, xi, n2, tw);
 }
 

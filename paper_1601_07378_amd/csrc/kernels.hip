@@ -111,15 +111,16 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
     }
 }
 
-// The same for twiddles held in LDS by the whole-plane kernel.  For an 8-point
-// first stage in FP64 only w^1, w^2 and w^4 are read; w^3, w^5, w^6 and w^7 are
-// their products (one or two roundings from the tabulated values): four complex
-// multiplies instead of four 16-byte LDS reads, for a kernel whose LDS traffic
-// is as long as its arithmetic.
-template <int R, int S, typename T>
+// The same with fewer table reads.  For an 8-point first stage only w^1, w^2
+// and w^4 are read; w^3, w^5, w^6 and w^7 are their products (one or two
+// roundings from the tabulated values): four complex multiplies instead of four
+// reads.  Used where reads are the scarcer resource: the FP64 whole-plane
+// kernel (LDS traffic as long as its arithmetic) and, with ANY, the stick
+// kernels of both precisions (memory-bound, arithmetic to spare).
+template <int R, int S, typename T, bool ANY = false>
 __device__ __forceinline__ void twiddle_lds(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
 {
-    if constexpr (R == 8 && std::is_same<T, double>::value) {
+    if constexpr (R == 8 && (ANY || std::is_same<T, double>::value)) {
         const cx<T> *w_n2 = tw + n2 * R;
         const cx<T> a = w_n2[1], b = w_n2[2], d = w_n2[4];
         auto mul = [](cx<T> u, cx<T> v) {
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
                 xi[n1] = v.y;
             }
             Dft<R, -1, T>::run(xr, xi);
-            twiddle<R, -1, T>(xr, xi, n2, tw);
+            twiddle_lds<R, -1, T, true>(xr, xi, n2, tw);
             cx<T> *line = lines + j * ldz + n2;
 #pragma unroll
             for (int k1 = 0; k1 < R; ++k1) line[L2 * k1] = mk<T>(xr[k1], xi[k1]);
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle<R, +1, T>(xr, xi, n2, tw);
+            twiddle_lds<R, +1, T, true>(xr, xi, n2, tw);
             Dft<R, +1, T>::run(xr, xi);
             if constexpr (GAM) {
                 // back into the line in natural z order (the task's own positions)

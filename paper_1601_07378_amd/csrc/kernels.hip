@@ -115,10 +115,11 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 // and w^4 are read; w^3, w^5, w^6 and w^7 are their products (one or two
 // roundings from the tabulated values): four complex multiplies instead of four
 // reads.  Used where reads are the scarcer resource: the FP64 whole-plane
-// kernel (LDS traffic as long as its arithmetic) and, with ANY, the stick
-// kernels of both precisions (memory-bound, arithmetic to spare).
+// kernel (its LDS traffic is as long as its arithmetic) and, with ANY, the
+// forward stick kernel in both precisions (its twiddle loads were a third of
+// its vector-memory instructions).
 template <int R, int S, typename T, bool ANY = false>
-__device__ __forceinline__ void twiddle_lds(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
+__device__ __forceinline__ void twiddle_pw(T *xr, T *xi, int n2, const cx<T> *__restrict__ tw)
 {
     if constexpr (R == 8 && (ANY || std::is_same<T, double>::value)) {
         const cx<T> *w_n2 = tw + n2 * R;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(512) void k_stick_fwd(Geometry g, DevTables t, Laun
                 xi[n1] = v.y;
             }
             Dft<R, -1, T>::run(xr, xi);
-            twiddle_lds<R, -1, T, true>(xr, xi, n2, tw);
+            twiddle_pw<R, -1, T, true>(xr, xi, n2, tw);
             cx<T> *line = lines + j * ldz + n2;
 #pragma unroll
             for (int k1 = 0; k1 < R; ++k1) line[L2 * k1] = mk<T>(xr[k1], xi[k1]);
@@ -300,10 +301,14 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
     const int s0 = gi.x, ns = gi.y;
     const int4 *slot_info = t.slot_info + sg.slot_off;
     cx<T> *ob = reinterpret_cast<cx<T> *>(sg.out) + (GAM ? 2 * bl : bl) * (long long)sg.npw;
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(t.twz);
     const int L1 = CZ1 ? CZ1 : g.L1z, L2 = CZ2 ? CZ2 : g.L2z;
     const int N3 = CZ1 ? CZ1 * CZ2 : g.N3, ldz = CZ1 ? CZ1 * CZ2 + 1 : g.ldz;
     const T inv_n = T(g.inv_n);
+    // stage twiddles into LDS after the stick lines (read after the barrier
+    // between stages B' and A')
+    cx<T> *tw = lines + g.group_cap * ldz;
+    const cx<T> *twg = reinterpret_cast<const cx<T> *>(t.twz);
+    for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = twg[i];
 
     with_size<CZ2>(L2, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
@@ -336,7 +341,7 @@ __global__ __launch_bounds__(512) void k_stick_bwd(Geometry g, DevTables t, Laun
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle_lds<R, +1, T, true>(xr, xi, n2, tw);
+            twiddle<R, +1, T>(xr, xi, n2, tw);
             Dft<R, +1, T>::run(xr, xi);
             if constexpr (GAM) {
                 // back into the line in natural z order (the task's own positions)
@@ -1211,7 +1216,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                     xi[n1] = pre[u * RY + n1].y;
                 }
                 Dft<RY, -1, T>::run(xr, xi);
-                twiddle_lds<RY, -1, T>(xr, xi, yn2[u], twy);
+                twiddle_pw<RY, -1, T>(xr, xi, yn2[u], twy);
 #pragma unroll
                 for (int k1 = 0; k1 < RY; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
             }
@@ -1243,7 +1248,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                         xi[n1] = v.y;
                     }
                     Dft<R, -1, T>::run(xr, xi);
-                    twiddle_lds<R, -1, T>(xr, xi, n2, twy);
+                    twiddle_pw<R, -1, T>(xr, xi, n2, twy);
 #pragma unroll
                     for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
                 }
@@ -1291,7 +1296,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xi[n1] = v.y;
             }
             Dft<R, -1, T>::run(xr, xi);
-            twiddle_lds<R, -1, T>(xr, xi, n2, twx);
+            twiddle_pw<R, -1, T>(xr, xi, n2, twx);
 #pragma unroll
             for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
         });
@@ -1364,7 +1369,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle_lds<R, +1, T>(xr, xi, n2, twx);
+            twiddle_pw<R, +1, T>(xr, xi, n2, twx);
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
@@ -1456,7 +1461,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle_lds<RY, +1, T>(xr, xi, yn2[u], twy);
+            twiddle_pw<RY, +1, T>(xr, xi, yn2[u], twy);
             Dft<RY, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < RY; ++n1) {
@@ -1480,7 +1485,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 xr[k1] = v.x;
                 xi[k1] = v.y;
             }
-            twiddle_lds<R, +1, T>(xr, xi, n2, twy);
+            twiddle_pw<R, +1, T>(xr, xi, n2, twy);
             Dft<R, +1, T>::run(xr, xi);
 #pragma unroll
             for (int n1 = 0; n1 < R; ++n1) {
@@ -1603,7 +1608,7 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch 
                             int threads, hipStream_t st)
 {
     if (L.nblk <= 0) return hipSuccess;
-    size_t lds = (size_t)g.group_cap * g.ldz * sizeof(cx<T>);
+    size_t lds = ((size_t)g.group_cap * g.ldz + g.N3) * sizeof(cx<T>);
     auto go = [&](auto kern) {
         hipError_t e = allow_lds(kern, lds);
         if (e != hipSuccess) return e;

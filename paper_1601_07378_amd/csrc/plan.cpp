@@ -350,6 +350,22 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
                                          : std::max(1, want_threads / tasks_per_stick);
     p.group_cap = std::min<int32_t>(p.group_cap, (int32_t)p.sticks.size());
     p.ldz = Lz + 1;
+    {
+        // the stick kernels keep a group's lines and the z-stage twiddles in LDS
+        const int64_t cap = (160 * 1024 / es - Lz) / (Lz + 1);
+        if (p.group_cap > cap) {
+            if (p.opt.sticks_per_group) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf,
+                         "sticks_per_group %d: the stick kernels' LDS holds at most %lld "
+                         "sticks of %d points",
+                         p.opt.sticks_per_group, (long long)cap, Lz);
+                err = buf;
+                return VLOC_E_INVALID;
+            }
+            p.group_cap = (int32_t)std::max<int64_t>(1, cap);
+        }
+    }
     const int64_t nst = p.nst();
 
     // ---- units of the deal: one stick, or in the real (gamma) mode a stick of

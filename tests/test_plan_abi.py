@@ -227,3 +227,22 @@ def test_gamma_validation():
     # apply's alias check covers the two half-sphere bands (2 x 463 coefficients)
     assert L.vloc_apply(p._h, fake, 2, ctypes.c_void_p(0x40000000),
                         ctypes.c_void_p(0x10000000 + 16 * 925)) == vloc.VLOC_E_ALIAS
+
+
+def test_stick_group_fits_lds():
+    """A stick workgroup keeps its group's z lines (N3 + 1 each) and the N3 stage
+    twiddles in the 160 KiB of LDS: at N3 = 256 that is at most 38 FP64 sticks or
+    77 FP32 ones.  An explicit larger group is rejected; the automatic choice stays
+    below the bound."""
+    grid, cell, ecut = (16, 16, 256), synth.cubic_cell(), 0.5 * 4.0 ** 2
+    p = vloc.Plan(grid, cell, ecut)
+    assert p.sticks().shape[0] >= 39
+    cap64 = (160 * 1024 // 16 - 256) // 257
+    assert cap64 == 38
+    assert p.layout()["sticks_per_group"] <= cap64
+    vloc.Plan(grid, cell, ecut, sticks_per_group=38)
+    with pytest.raises(vloc.VlocError) as e:
+        vloc.Plan(grid, cell, ecut, sticks_per_group=39)
+    assert e.value.status == vloc.VLOC_E_INVALID
+    assert "LDS" in str(e.value)
+    vloc.Plan(grid, cell, ecut, precision="f32", sticks_per_group=39)

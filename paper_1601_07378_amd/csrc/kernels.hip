@@ -1523,22 +1523,30 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
 // VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)
 // + y / L1y: the potential in the order the full-plane kernel's x stage B
 // reads it (each task's L2x values contiguous, tasks along yp adjacent).
+// One workgroup per (z, block of kArrangeRows consecutive yp): the rows are
+// read whole (coalesced) into LDS, then every (k1, yp, k2) run of the block,
+// kArrangeRows * L2x contiguous values per k1, is written out.
+constexpr int kArrangeRows = 8;
 template <typename T>
 __global__ void k_arrange_v(const T *__restrict__ V, T *__restrict__ VT, int N1, int N2, int N3,
                             int L1x, int L2x, int L1y, int L2y)
 {
-    const long long n = (long long)N1 * N2 * N3;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long r = i / L2x;
-        const int k2 = (int)(i - r * L2x);
-        const long long q = r / N2;
-        const int yp = (int)(r - q * N2);
-        const long long z = q / L1x;
-        const int k1 = (int)(q - z * L1x);
-        const int x = k1 + L1x * k2;
-        const int y = (yp % L2y) * L1y + yp / L2y;
-        VT[i] = V[(z * N2 + y) * N1 + x];
+    extern __shared__ unsigned char smem_raw[];
+    T *rows = reinterpret_cast<T *>(smem_raw); // [kArrangeRows][N1]
+    const int nyb = (N2 + kArrangeRows - 1) / kArrangeRows;
+    const int z = blockIdx.x / nyb, yp0 = (blockIdx.x - z * nyb) * kArrangeRows;
+    const int nr = min(kArrangeRows, N2 - yp0);
+    for (int t = threadIdx.x; t < nr * N1; t += blockDim.x) {
+        const int r = t / N1, x = t - r * N1;
+        const int yp = yp0 + r, y = (yp % L2y) * L1y + yp / L2y;
+        rows[t] = V[((long long)z * N2 + y) * N1 + x];
+    }
+    __syncthreads();
+    const int run = nr * L2x;
+    for (int t = threadIdx.x; t < L1x * run; t += blockDim.x) {
+        const int k1 = t / run, u = t - k1 * run;
+        const int r = u / L2x, k2 = u - r * L2x;
+        VT[(((long long)z * L1x + k1) * N2 + yp0 + r) * L2x + k2] = rows[r * N1 + k1 + L1x * k2];
     }
 }
 
@@ -1789,9 +1797,9 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
 template <typename T>
 hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStream_t st)
 {
-    const long long n = (long long)g.N1 * g.N2 * g.N3;
-    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_arrange_v<T>, dim3(blocks), dim3(256), 0, st,
+    const int nyb = (g.N2 + kArrangeRows - 1) / kArrangeRows;
+    const size_t lds = (size_t)kArrangeRows * g.N1 * sizeof(T);
+    hipLaunchKernelGGL(k_arrange_v<T>, dim3((unsigned)(g.N3 * nyb)), dim3(256), lds, st,
                        reinterpret_cast<const T *>(V), reinterpret_cast<T *>(VT), g.N1, g.N2,
                        g.N3, g.L1x, g.L2x, g.L1y, g.L2y);
     return hipGetLastError();

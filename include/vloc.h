@@ -50,7 +50,9 @@ typedef struct vloc_plan_s *vloc_plan; /* opaque; owned by the library */
 typedef enum {
     VLOC_OK = 0,
     VLOC_E_INVALID = -1, /* NULL pointer, negative count, bad option            */
-    VLOC_E_GRID = -2,    /* N_i < 1, N_i > 256, or a length the FFT cannot split */
+    VLOC_E_GRID = -2,    /* N_i < 1, N_i > 960, a prime factor other than 2, 3,  */
+                         /* 5, or one z-plane's occupied part too large for the  */
+                         /* plane kernel's 160 KiB of LDS                        */
     VLOC_E_CELL = -3,    /* det(cell) <= 0 or non-finite cell                    */
     VLOC_E_SPHERE = -4,  /* empty sphere, bad Ecut/k, or the sphere's extent on  */
                          /* some axis is >= N_i (two points alias on the grid)  */
@@ -96,7 +98,9 @@ typedef struct {
     int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
                                  each axis (x, y, z); 0 = automatic (the most
                                  balanced split); else L1 and L / L1 must both be
-                                 codelet lengths {1..6, 8, 9, 10, 12, 15, 16}.
+                                 codelet lengths {1..6, 8, 9, 10, 12, 15, 16, 18,
+                                 20, 24, 25, 27, 30, 32} (x and y codelets above 16
+                                 need plane_threads <= 512).
                                  Common grids run kernels compiled for their
                                  automatic split; other splits run the same
                                  kernels with run-time sizes                       */
@@ -112,9 +116,11 @@ typedef struct {
 } vloc_options;
 
 /* Build a plan (host work only; device tables are uploaded on first use).
- *   grid : {N1, N2, N3}, each in [1, 256] and a product L1*L2 of factors
- *          in {1,2,3,4,5,6,8,9,10,12,15,16} (every 2,3,5-smooth length up to
- *          256 except 125, 243 and 250).
+ *   grid : {N1, N2, N3}, each in [1, 960] with no prime factor other than 2,
+ *          3 and 5 (the FFT grids of a plane-wave code, Sec. 2: every such
+ *          length splits into two register codelets of at most 32 points).
+ *          One z-plane's occupied part, nxo (N2 + 1) complex values plus one
+ *          row buffer, must fit in 160 KiB of LDS (else VLOC_E_GRID).
  *   cell : rows a1, a2, a3 (bohr), det > 0.
  *   ecut : Hartree; the sphere keeps |k+G|^2 <= 2 ecut (1 + 1e-12).
  *   k    : reduced coordinates in the reciprocal basis b1, b2, b3.
@@ -130,7 +136,9 @@ vloc_status vloc_plan_create_ex(vloc_plan *plan, const int32_t grid[3], const do
 vloc_status vloc_plan_destroy(vloc_plan plan);
 
 /* Stream on which the plan enqueues work (a hipStream_t; NULL = the null
- * stream).  The plan does not own the stream. */
+ * stream).  The plan does not own the stream.  The plan's stick buffer is
+ * reused by every call, so on a change of stream the new stream first waits
+ * (hipStreamWaitEvent) for the work already enqueued on the old one. */
 vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream);
 
 /* out[n] = V_loc c[n] for n < nbands (definition above).  Stream-ordered and

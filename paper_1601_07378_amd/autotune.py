@@ -23,7 +23,7 @@ import numpy as np
 
 from . import vloc
 
-CODELETS = (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16)
+CODELETS = (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32)
 
 
 def axis_splits(L: int) -> List[int]:

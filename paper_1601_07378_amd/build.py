@@ -3,7 +3,8 @@
 All device code is compiled with packed FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``) and with
 ``-fno-signed-zeros`` so that additions of known zeros fold away.  Sources
-compile to objects in parallel (the transform kernels once per precision)
+compile to objects in parallel (the transform kernels once per precision and
+launcher part)
 and are linked into one shared library.
 """
 import os
@@ -19,8 +20,10 @@ OBJDIR = os.path.join(PKG, "_build")
 ARCH = os.environ.get("VLOC_OFFLOAD_ARCH", "gfx950")
 # (source, object, extra defines)
 UNITS = [
-    ("kernels.hip", "kernels_f64.o", ["-DVLOC_ONLY_F64"]),
-    ("kernels.hip", "kernels_f32.o", ["-DVLOC_ONLY_F32"]),
+    ("kernels.hip", f"kernels_{prec}_{part}.o", [f"-DVLOC_ONLY_{prec.upper()}",
+                                                 f"-DVLOC_PART_{part.upper()}"])
+    for prec in ("f64", "f32") for part in ("full_apply", "full_aux", "rows", "stick")
+] + [
     ("reduce.hip", "reduce.o", []),
     ("plan.cpp", "plan.o", []),
     ("api.cpp", "api.o", []),

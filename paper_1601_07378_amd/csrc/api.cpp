@@ -33,9 +33,10 @@ struct Engine {
     int2 *d_cols = nullptr;
     int4 *d_gam = nullptr;
     int *d_yslot = nullptr;
+    int *d_holes = nullptr;
     void *d_tw[3] = {nullptr, nullptr, nullptr};
     double2 *d_twx64 = nullptr;
-    std::vector<int> slot_off, group_off, col_off;
+    std::vector<int> slot_off, group_off, col_off, hole_off, nholes;
     void *d_S = nullptr;
     size_t S_bytes = 0;
     double *d_partial = nullptr; // density partial planes
@@ -47,6 +48,8 @@ struct Engine {
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
     std::vector<int> rec_modes;
+    // orders work across a change of stream (the stick buffer is reused)
+    hipEvent_t order_ev = nullptr;
 };
 
 struct vloc_plan_s {
@@ -99,6 +102,7 @@ void free_device(Engine &E)
     free_ptr(E.d_cols);
     free_ptr(E.d_gam);
     free_ptr(E.d_yslot);
+    free_ptr(E.d_holes);
     free_ptr(E.d_twx64);
     for (void *&t : E.d_tw) free_ptr(t);
     free_ptr(E.d_S);
@@ -118,6 +122,27 @@ void release(Engine &E)
         for (hipEvent_t e : E.events) (void)hipEventDestroy(e);
         E.events.clear();
     }
+    if (E.order_ev) {
+        (void)hipEventDestroy(E.order_ev);
+        E.order_ev = nullptr;
+    }
+}
+
+// Makes `s` the engine's stream.  Work already enqueued on the old stream
+// uses the engine's stick buffer and arranged potential, which the next call
+// reuses: the new stream first waits for everything queued on the old one.
+vloc_status switch_stream(Engine &E, hipStream_t s)
+{
+    if (s == E.stream) return VLOC_OK;
+    if (E.uploaded || E.d_S) {
+        hipError_t e = hipSuccess;
+        if (!E.order_ev) e = hipEventCreateWithFlags(&E.order_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(E.order_ev, E.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, E.order_ev, 0);
+        if (e != hipSuccess) return hip_fail(e, "ordering the stream change");
+    }
+    E.stream = s;
+    return VLOC_OK;
 }
 
 template <typename V>
@@ -141,15 +166,27 @@ vloc_status upload(Engine &E)
     // member tables, concatenated: slots and groups relative to the member
     std::vector<int4> slot, gam;
     std::vector<int2> groups, cols;
-    std::vector<int> yslot;
+    std::vector<int> yslot, holes;
     E.slot_off.clear();
     E.group_off.clear();
     E.col_off.clear();
+    E.hole_off.clear();
+    E.nholes.clear();
     int cap = 0;
     for (const HostPlan *m : E.members) {
         E.slot_off.push_back((int)slot.size());
         E.group_off.push_back((int)groups.size());
         E.col_off.push_back((int)cols.size());
+        E.hole_off.push_back((int)holes.size());
+        E.nholes.push_back((int)(m->holes.size() / 2));
+        for (size_t i = 0; i + 1 < m->holes.size(); i += 2) {
+            const int32_t hh = m->holes[i], kk = m->holes[i + 1];
+            int kp = kk % m->grid[1];
+            if (kp < 0) kp += m->grid[1];
+            int col = hh - m->hmin;
+            if (m->plane_full) col = ((hh % m->grid[0]) + m->grid[0]) % m->grid[0];
+            holes.push_back(col * m->ldy + kp);
+        }
         for (int64_t s = 0; s < m->nst(); ++s) {
             const Stick &st = m->sticks[m->stick_of_slot[s]];
             int lm = st.lmin % m->grid[2];
@@ -200,6 +237,7 @@ vloc_status upload(Engine &E)
     if ((e = upload_vec(E.d_cols, cols)) != hipSuccess) goto devfail;
     if (!gam.empty() && (e = upload_vec(E.d_gam, gam)) != hipSuccess) goto devfail;
     if (!yslot.empty() && (e = upload_vec(E.d_yslot, yslot)) != hipSuccess) goto devfail;
+    if (!holes.empty() && (e = upload_vec(E.d_holes, holes)) != hipSuccess) goto devfail;
     if (h.plane_full) {
         const size_t vbytes = (size_t)h.grid[0] * h.grid[1] * h.grid[2] * (h.elem_bytes() / 2);
         if ((e = hipMalloc(&E.d_VT, vbytes)) != hipSuccess) goto devfail;
@@ -253,7 +291,6 @@ vloc_status upload(Engine &E)
         g.ldy = h.ldy;
         g.ldx = h.ldx;
         g.ldz = h.ldz;
-        g.rows = h.plane_rows;
         g.rb = h.plane_rb;
         g.rl = h.plane_rl;
         g.xw = h.plane_xw;
@@ -327,6 +364,7 @@ DevTables tables(const Engine &E)
     t.wts = nullptr;
     t.gam = E.d_gam;
     t.yslot = E.d_yslot;
+    t.holes = E.d_holes;
     return t;
 }
 
@@ -388,6 +426,8 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
             s.slot_off = E.slot_off[p.member];
             s.group_off = E.group_off[p.member];
             s.col_off = E.col_off[p.member];
+            s.hole_off = E.hole_off[p.member];
+            s.nholes = E.nholes[p.member];
             s.band_lo = band_lo;
             s.nb = p.nb;
             s.blk_lo = blk_lo;
@@ -566,8 +606,7 @@ vloc_status vloc_plan_destroy(vloc_plan plan)
 vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream)
 {
     if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
-    plan->eng.stream = reinterpret_cast<hipStream_t>(hip_stream);
-    return VLOC_OK;
+    return switch_stream(plan->eng, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void *V, void *out)
@@ -891,8 +930,7 @@ vloc_status vloc_batch_plan(vloc_batch batch, int32_t ik, vloc_plan *plan)
 vloc_status vloc_batch_set_stream(vloc_batch batch, void *hip_stream)
 {
     if (!batch) return fail(VLOC_E_INVALID, "batch is NULL");
-    batch->eng.stream = reinterpret_cast<hipStream_t>(hip_stream);
-    return VLOC_OK;
+    return switch_stream(batch->eng, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 vloc_status vloc_batch_use_graph(vloc_batch batch, int32_t enable)

@@ -1,12 +1,12 @@
 // dft_codelets.h -- small complex DFTs held entirely in registers.
 //
-//   X[k] = sum_{n<R} x[n] exp(S 2 pi i n k / R),  S = -1 or +1,  R <= 16.
+//   X[k] = sum_{n<R} x[n] exp(S 2 pi i n k / R),  S = -1 or +1,  R <= 32.
 //
 // Primes 2, 3, 5 and the radix 4 are written out from the definition; sizes
-// with coprime factors (6, 10, 12, 15) use the prime-factor mapping (no
-// twiddles); 8, 9 and 16 are split R = P*Q (P = 4 when 4 | R and R > 4, else
-// the smallest prime) by decimation in time with twiddles that are
-// compile-time constants.
+// with coprime factors (6, 10, 12, 15, 18, 20, 24, 30) use the prime-factor
+// mapping (no twiddles); 8, 9, 16, 25, 27 and 32 are split R = P*Q (P = 4
+// when 4 | R and R > 4, else the smallest prime) by decimation in time with
+// twiddles that are compile-time constants.
 // The constants come from a constexpr sine/cosine: exact integer reduction of
 // the angle numerator to the first half-quadrant, then a Taylor series.
 #pragma once
@@ -315,12 +315,21 @@ template <int S, typename T>
 struct Dft<12, S, T> : Pfa<4, 3, S, T> {};
 template <int S, typename T>
 struct Dft<15, S, T> : Pfa<3, 5, S, T> {};
+template <int S, typename T>
+struct Dft<18, S, T> : Pfa<2, 9, S, T> {};
+template <int S, typename T>
+struct Dft<20, S, T> : Pfa<4, 5, S, T> {};
+template <int S, typename T>
+struct Dft<24, S, T> : Pfa<8, 3, S, T> {};
+template <int S, typename T>
+struct Dft<30, S, T> : Pfa<2, 15, S, T> {};
 
 // Sizes a plan may use for the two factors of a line length.
 __host__ __device__ constexpr bool codelet_supported(int R)
 {
     return R == 1 || R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 ||
-           R == 10 || R == 12 || R == 15 || R == 16;
+           R == 10 || R == 12 || R == 15 || R == 16 || R == 18 || R == 20 || R == 24 ||
+           R == 25 || R == 27 || R == 30 || R == 32;
 }
 
 } // namespace vloc

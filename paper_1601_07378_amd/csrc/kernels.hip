@@ -53,10 +53,24 @@ __device__ __forceinline__ cx<T> mk(T a, T b)
     return v;
 }
 
-// Calls f with a compile-time codelet size equal to the runtime r.
-template <typename F>
+// Calls f with a compile-time codelet size equal to the runtime r.  Sizes
+// above MAXR are not compiled (workgroups of more than 512 threads have too
+// few registers for them); the launchers never run such a kernel with them.
+template <int MAXR = 32, typename F>
 __device__ __forceinline__ void with_codelet(int r, F &&f)
 {
+    if constexpr (MAXR > 16) {
+        switch (r) {
+        case 18: f(std::integral_constant<int, 18>{}); return;
+        case 20: f(std::integral_constant<int, 20>{}); return;
+        case 24: f(std::integral_constant<int, 24>{}); return;
+        case 25: f(std::integral_constant<int, 25>{}); return;
+        case 27: f(std::integral_constant<int, 27>{}); return;
+        case 30: f(std::integral_constant<int, 30>{}); return;
+        case 32: f(std::integral_constant<int, 32>{}); return;
+        default: break;
+        }
+    }
     switch (r) {
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
@@ -75,13 +89,13 @@ __device__ __forceinline__ void with_codelet(int r, F &&f)
 }
 
 // Compile-time size CT if non-zero, else the runtime r through the switch.
-template <int CT, typename F>
+template <int CT, int MAXR = 32, typename F>
 __device__ __forceinline__ void with_size(int r, F &&f)
 {
     if constexpr (CT > 0)
         f(std::integral_constant<int, CT>{});
     else
-        with_codelet(r, f);
+        with_codelet<MAXR>(r, f);
 }
 
 // Bit n1 of a zero mask ZM is set when every input x[n2 + L2 n1] of stage A
@@ -566,7 +580,7 @@ __device__ __forceinline__ void quad_twiddle(T *xr, T *xi, int q, int L,
 }
 
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int ZY, int XQ,
-          int PF>
+          int PF, int MR>
 __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t, const Launch &L,
                                            cx<T> *__restrict__ S, const T *__restrict__ V,
                                            cx<T> *__restrict__ psi, long long band0)
@@ -702,6 +716,8 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         for (int i = 0; i < PF; ++i)
             if (tid + i * nthr < nst) plane[spos[i]] = sval[i];
         for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
+        for (int i = tid; i < sg.nholes; i += nthr)
+            plane[t.holes[sg.hole_off + i]] = mk<T>(T(0), T(0));
         __syncthreads();
         {
             int jn = jc, kn = kc, zz, bb;
@@ -711,7 +727,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             }
         }
         // y forward, stage A (lanes along columns)
-        with_size<CY1>(L1y, [&](auto RC) {
+        with_size<CY1, MR>(L1y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L2y; task += nthr) {
                 const int n2 = div_nxo(task), hc = task - n2 * nxo;
@@ -739,7 +755,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         });
         __syncthreads();
         // y forward, stage B (lanes along columns)
-        with_size<CY2>(L2y, [&](auto RC) {
+        with_size<CY2, MR>(L2y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L1y; task += nthr) {
                 const int k1 = div_nxo(task), hc = task - k1 * nxo;
@@ -819,7 +835,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
         for (int y0 = ybeg; y0 < yend; y0 += RB) {
             const int nr = min(RB, yend - y0);
             if (MODE != MODE_R2G) {
-                with_size<CX1>(L1x, [&](auto RC) {
+                with_size<CX1, MR>(L1x, [&](auto RC) {
                     constexpr int R = decltype(RC)::value;
                     for (int task = lane; task < nr * L2x; task += 64) {
                         const int r = task / L2x, n2 = task - r * L2x;
@@ -846,7 +862,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                 });
                 wave_sync();
             }
-            with_size<CX2>(L2x, [&](auto RC) {
+            with_size<CX2, MR>(L2x, [&](auto RC) {
                 constexpr int R = decltype(RC)::value;
                 for (int task = lane; task < nr * L1x; task += 64) {
                     const int r = task / L1x, k1 = task - r * L1x;
@@ -906,7 +922,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
             });
             wave_sync();
             if (MODE != MODE_G2R && MODE != MODE_DENSITY) {
-                with_size<CX1>(L1x, [&](auto RC) {
+                with_size<CX1, MR>(L1x, [&](auto RC) {
                     constexpr int R = decltype(RC)::value;
                     for (int task = lane; task < nr * L2x; task += 64) {
                         const int r = task / L2x, n2 = task - r * L2x;
@@ -939,7 +955,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     if (MODE == MODE_G2R || MODE == MODE_DENSITY) continue;
 
     // y reverse, stage B' (lanes along columns)
-    with_size<CY2>(L2y, [&](auto RC) {
+    with_size<CY2, MR>(L2y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L1y; task += nthr) {
             const int k1 = div_nxo(task), hc = task - k1 * nxo;
@@ -958,7 +974,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     });
     __syncthreads();
     // y reverse, stage A' (lanes along columns): only stick positions are kept
-    with_size<CY1>(L1y, [&](auto RC) {
+    with_size<CY1, MR>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
             const int n2 = div_nxo(task), hc = task - n2 * nxo;
@@ -998,7 +1014,7 @@ __global__ __launch_bounds__(512) void k_plane(Geometry g, DevTables t, Launch L
                                                cx<T> *__restrict__ S, const T *__restrict__ V,
                                                cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 4>(g, t, L, S, V, psi, band0);
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 4, 32>(g, t, L, S, V, psi, band0);
 }
 
 // The same with up to 1024 threads (16 waves: more latency hiding for FP64,
@@ -1010,7 +1026,7 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
                                                      const T *__restrict__ V,
                                                      cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 2>(g, t, L, S, V, psi, band0);
+    plane_body<T, MODE, CX1, CX2, CY1, CY2, ZX, ZY, 0, 2, 16>(g, t, L, S, V, psi, band0);
 }
 
 // ------------------------------------------------------- K2, full plane
@@ -1025,7 +1041,7 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
 // may hold stale values: they are never read as input.  The potential comes
 // pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
-          bool WPR, int YT>
+          bool WPR, int YT, int MR>
 __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
                                                 const Launch &L, cx<T> *__restrict__ S,
                                                 const T *__restrict__ VT,
@@ -1225,9 +1241,11 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             for (int i = 0; i < PF; ++i)
                 if (tid + i * nthr < nst) plane[pos[i]] = pre[i];
             for (int sl = tid + PF * nthr; sl < nst; sl += nthr) plane[slots[sl].w] = Sz[sl];
+            for (int i = tid; i < sg.nholes; i += nthr)
+                plane[t.holes[sg.hole_off + i]] = mk<T>(T(0), T(0));
             __syncthreads();
             // y forward, stage A (lanes along occupied columns)
-            with_size<CY1>(L1y, [&](auto RC) {
+            with_size<CY1, MR>(L1y, [&](auto RC) {
                 constexpr int R = decltype(RC)::value;
                 for (int task = tid; task < nxo * L2y; task += nthr) {
                     const int n2 = div_nxo(task), hc = task - n2 * nxo;
@@ -1256,7 +1274,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         }
         __syncthreads();
         // y forward, stage B
-        with_size<CY2>(L2y, [&](auto RC) {
+        with_size<CY2, MR>(L2y, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             for (int task = tid; task < nxo * L1y; task += nthr) {
                 const int k1 = div_nxo(task), hc = task - k1 * nxo;
@@ -1281,7 +1299,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     // potential, the density or the real-space values; stage_a2: reverse stage
     // A', occupied outputs only.  All in place in P.
     auto stage_a = [&](int n2, int yp) {
-        with_size<CX1>(L1x, [&](auto RC) {
+        with_size<CX1, MR>(L1x, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + n2 * ldy + yp;
             T xr[R], xi[R];
@@ -1302,7 +1320,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         });
     };
     auto stage_b = [&](int k1, int yp) {
-        with_size<CX2>(L2x, [&](auto RC) {
+        with_size<CX2, MR>(L2x, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + L2x * k1 * ldy + yp;
             T xr[R], xi[R];
@@ -1359,7 +1377,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         });
     };
     auto stage_a2 = [&](int n2, int yp) {
-        with_size<CX1>(L1x, [&](auto RC) {
+        with_size<CX1, MR>(L1x, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + n2 * ldy + yp;
             T xr[R], xi[R];
@@ -1429,7 +1447,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         __syncthreads();
     }
     // y reverse, stage B'
-    with_size<CY2>(L2y, [&](auto RC) {
+    with_size<CY2, MR>(L2y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L1y; task += nthr) {
             const int k1 = div_nxo(task), hc = task - k1 * nxo;
@@ -1472,7 +1490,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         continue;
     }
     // y reverse, stage A': only stick positions are kept
-    with_size<CY1>(L1y, [&](auto RC) {
+    with_size<CY1, MR>(L1y, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
         for (int task = tid; task < nxo * L2y; task += nthr) {
             const int n2 = div_nxo(task), hc = task - n2 * nxo;
@@ -1516,7 +1534,8 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
                                                      cx<T> *__restrict__ psi, long long band0)
 {
     // prefetched slots per thread cover 2048 slots
-    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR, YT>(
+    plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR, YT,
+                    (MAXT > 512 ? 16 : 32)>(
         g, t, L, S, VT, psi, band0);
 }
 
@@ -1557,14 +1576,31 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per
 void k_plane_quad(Geometry g, DevTables t, Launch L, cx<T> *__restrict__ S,
                   const T *__restrict__ V, cx<T> *__restrict__ psi, long long band0)
 {
-    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ, 4>(g, t, L, S, V, psi, band0);
+    plane_body<T, MODE, 0, 0, CY1, CY2, 0, 0, XQ, 4, 16>(g, t, L, S, V, psi, band0);
 }
 
 // ------------------------------------------------------------ launchers
+//
+// The launchers are compiled in parts, each part once per precision, so that
+// the build runs them in parallel: VLOC_PART_STICK (stick kernels, potential
+// arrangement and the plane-kernel dispatch), VLOC_PART_FULL_APPLY and
+// VLOC_PART_FULL_AUX (whole-plane kernels of the application, and of the
+// diagnostic transforms and the density) and VLOC_PART_ROWS (row-buffer and
+// lane-quad kernels).  Without a part macro everything is compiled.
+#if !defined(VLOC_PART_STICK) && !defined(VLOC_PART_FULL_APPLY) &&                               \
+    !defined(VLOC_PART_FULL_AUX) && !defined(VLOC_PART_ROWS)
+#define VLOC_PART_STICK
+#define VLOC_PART_FULL_APPLY
+#define VLOC_PART_FULL_AUX
+#define VLOC_PART_ROWS
+#endif
+#if defined(VLOC_PART_FULL_APPLY) || defined(VLOC_PART_FULL_AUX)
+#define VLOC_PART_FULL
+#endif
 
 // Persistent plane grid: the workgroups that are resident at once (a
 // multiple of 8 so that the XCD schedule applies), never more than the planes.
-static unsigned plane_blocks(const Geometry &g, int nb)
+[[maybe_unused]] static unsigned plane_blocks(const Geometry &g, int nb)
 {
     long long total = (long long)nb * g.N3;
     long long res = (long long)g.resident_plane_wgs;
@@ -1581,6 +1617,14 @@ static hipError_t allow_lds(K kernel, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Largest codelet of the plane kernel's x and y splits: kernels of more than
+// 512 threads are compiled for codelets of at most 16 points.
+[[maybe_unused]] static int plane_codelet_max(const Geometry &g)
+{
+    return std::max(std::max(g.L1x, g.L2x), std::max(g.L1y, g.L2y));
+}
+
+#if defined(VLOC_PART_STICK)
 // Line splits and zero masks compiled as specialisations of the stick
 // kernels; any other plan runs the same kernels with runtime sizes.  A
 // specialisation serves every plan whose zero mask contains its own (it then
@@ -1631,7 +1675,9 @@ hipError_t launch_stick_bwd(const Geometry &g, const DevTables &t, const Launch 
 #undef VLOC_K3
     return g.gamma ? go(k_stick_bwd<T, 0, 0, 0, true>) : go(k_stick_bwd<T, 0, 0, 0, false>);
 }
+#endif // VLOC_PART_STICK
 
+#if defined(VLOC_PART_ROWS)
 template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int ZY>
 static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, const Launch &L,
                                      void *S, const void *V, void *psi, int64_t band0,
@@ -1646,9 +1692,10 @@ static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, cons
         return hipGetLastError();
     };
     if (threads <= 512) return go(k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
-    // wide workgroups: compiled for FP64 application and density only
+    // wide workgroups: compiled for FP64 application and density only, with
+    // codelets of at most 16 points
     if constexpr (std::is_same<T, double>::value && (MODE == MODE_APPLY || MODE == MODE_DENSITY))
-        return go(k_plane_wide<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
+        if (plane_codelet_max(g) <= 16) return go(k_plane_wide<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
     return hipErrorInvalidValue;
 }
 
@@ -1666,80 +1713,14 @@ static hipError_t launch_plane_quad(const Geometry &g, const DevTables &t, const
     return hipGetLastError();
 }
 
-template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY>
-static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const Launch &L,
-                                    void *S, const void *VT, void *psi, int64_t band0,
-                                    int threads, int lds, hipStream_t st)
-{
-    auto go = [&](auto kern, int nthr) {
-        hipError_t e = allow_lds(kern, (size_t)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(nthr), (size_t)lds, st, g, t,
-                           L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(VT),
-                           reinterpret_cast<cx<T> *>(psi), (long long)band0);
-        return hipGetLastError();
-    };
-    // direct y form: one segment, a specialised y split, apply (and FP32
-    // density; the FP64 density kernel would spill with it)
-    constexpr bool DYK = Y1 > 0 && (MODE == MODE_APPLY ||
-                                    (MODE == MODE_DENSITY && std::is_same<T, float>::value));
-    const bool dyok = DYK && L.nseg == 1;
-    auto pick = [&](auto wpr) {
-        constexpr bool W = decltype(wpr)::value;
-        // more than 512 threads: compiled for FP64 application and density; the
-        // diagnostic transforms run the same body on 512 threads
-        if constexpr (std::is_same<T, double>::value &&
-                      (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
-            const bool dy1 = !W && dyok && g.nxo * g.L2y <= threads;
-            if (threads > 768) {
-                if constexpr (DYK && !W)
-                    if (dy1)
-                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1>,
-                                  threads);
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0>, threads);
-            }
-            if (threads > 512) {
-                if constexpr (DYK && !W)
-                    if (dy1)
-                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 1>,
-                                  threads);
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 0>, threads);
-            }
-        }
-        const int nt = threads < 512 ? threads : 512;
-        if constexpr (DYK && !W && std::is_same<T, float>::value)
-            if (dyok && g.nxo * g.L2y <= 2 * nt)
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2>, nt);
-        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0>, nt);
-    };
-    if (g.full == 2) return pick(std::true_type{});
-    return pick(std::false_type{});
-}
-
-// Specialised line splits for the common grids; any other split runs the same
-// kernel with runtime sizes.  A specialisation serves every plan whose zero
-// masks contain its own.
+// Row-buffer and lane-quad layouts.  Specialised line splits for the common
+// grids; any other split runs the same kernel with runtime sizes.  A
+// specialisation serves every plan whose zero masks contain its own.
 template <typename T, int MODE>
-static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const Launch &L,
-                                    void *S, const void *V, void *psi, int64_t band0,
-                                    int threads, int lds, hipStream_t st)
+hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                                  const void *V, void *psi, int64_t band0, int threads, int lds,
+                                  hipStream_t st)
 {
-    if (g.full) {
-#define VLOC_FULL_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                 \
-        if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&      \
-            (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                               \
-            return launch_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY>(g, t, L, S, V, psi,      \
-                                                                         band0, threads, lds, st);
-        VLOC_FULL_CASE(8, 12, 8, 12, 0x38, 0xC3, 0x38)
-        VLOC_FULL_CASE(12, 8, 8, 12, 0x1F0, 0xE07, 0x38)
-        VLOC_FULL_CASE(8, 9, 8, 12, 0x38, 0xC3, 0x3C)
-        VLOC_FULL_CASE(8, 16, 8, 16, 0x38, 0xC3, 0x38)
-        VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
-        VLOC_FULL_CASE(4, 6, 4, 6, 0x4, 0x9, 0x4)
-#undef VLOC_FULL_CASE
-        return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
-                                                               lds, st);
-    }
     if constexpr (MODE != MODE_DENSITY) if (g.xq) {
 #define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
         if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
@@ -1771,7 +1752,86 @@ static hipError_t launch_plane_mode(const Geometry &g, const DevTables &t, const
     return launch_plane_sized<T, MODE, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads, lds,
                                                          st);
 }
+#endif // VLOC_PART_ROWS
 
+#if defined(VLOC_PART_FULL)
+template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY>
+static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const Launch &L,
+                                    void *S, const void *VT, void *psi, int64_t band0,
+                                    int threads, int lds, hipStream_t st)
+{
+    auto go = [&](auto kern, int nthr) {
+        hipError_t e = allow_lds(kern, (size_t)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(nthr), (size_t)lds, st, g, t,
+                           L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(VT),
+                           reinterpret_cast<cx<T> *>(psi), (long long)band0);
+        return hipGetLastError();
+    };
+    // direct y form: one segment, a specialised y split, apply (and FP32
+    // density; the FP64 density kernel would spill with it)
+    constexpr bool DYK = Y1 > 0 && (MODE == MODE_APPLY ||
+                                    (MODE == MODE_DENSITY && std::is_same<T, float>::value));
+    const bool dyok = DYK && L.nseg == 1;
+    auto pick = [&](auto wpr) {
+        constexpr bool W = decltype(wpr)::value;
+        // more than 512 threads: compiled for FP64 application and density with
+        // codelets of at most 16 points; the diagnostic transforms run the same
+        // body on 512 threads
+        if constexpr (std::is_same<T, double>::value &&
+                      (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
+            const bool dy1 = !W && dyok && g.nxo * g.L2y <= threads;
+            if (threads > 512 && plane_codelet_max(g) > 16) return hipErrorInvalidValue;
+            if (threads > 768) {
+                if constexpr (DYK && !W)
+                    if (dy1)
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1>,
+                                  threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0>, threads);
+            }
+            if (threads > 512) {
+                if constexpr (DYK && !W)
+                    if (dy1)
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 1>,
+                                  threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 0>, threads);
+            }
+        }
+        const int nt = threads < 512 ? threads : 512;
+        if constexpr (DYK && !W && std::is_same<T, float>::value)
+            if (dyok && g.nxo * g.L2y <= 2 * nt)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2>, nt);
+        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0>, nt);
+    };
+    if (g.full == 2) return pick(std::true_type{});
+    return pick(std::false_type{});
+}
+
+// Whole-plane layout.  Specialised line splits for the common grids; any
+// other split runs the same kernel with runtime sizes.
+template <typename T, int MODE>
+hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                                  const void *V, void *psi, int64_t band0, int threads, int lds,
+                                  hipStream_t st)
+{
+#define VLOC_FULL_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                 \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
+        (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                                   \
+        return launch_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY>(g, t, L, S, V, psi, band0,   \
+                                                                     threads, lds, st);
+    VLOC_FULL_CASE(8, 12, 8, 12, 0x38, 0xC3, 0x38)
+    VLOC_FULL_CASE(12, 8, 8, 12, 0x1F0, 0xE07, 0x38)
+    VLOC_FULL_CASE(8, 9, 8, 12, 0x38, 0xC3, 0x3C)
+    VLOC_FULL_CASE(8, 16, 8, 16, 0x38, 0xC3, 0x38)
+    VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
+    VLOC_FULL_CASE(4, 6, 4, 6, 0x4, 0x9, 0x4)
+#undef VLOC_FULL_CASE
+    return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
+                                                           lds, st);
+}
+#endif // VLOC_PART_FULL
+
+#if defined(VLOC_PART_STICK)
 template <typename T>
 hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, int mode, void *S,
                         const void *V, void *psi, int64_t band0, int threads, int lds_bytes,
@@ -1779,17 +1839,19 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
 {
     if (L.nbt <= 0) return hipSuccess;
     if (mode != MODE_APPLY && L.nseg != 1) return hipErrorInvalidValue;
+    if (mode == MODE_DENSITY && g.xq) return hipErrorInvalidValue; // row-buffer x pass only
+    auto run = [&](auto m) {
+        constexpr int M = decltype(m)::value;
+        return g.full ? launch_plane_full_mode<T, M>(g, t, L, S, V, psi, band0, threads,
+                                                     lds_bytes, st)
+                      : launch_plane_rows_mode<T, M>(g, t, L, S, V, psi, band0, threads,
+                                                     lds_bytes, st);
+    };
     switch (mode) {
-    case MODE_APPLY:
-        return launch_plane_mode<T, MODE_APPLY>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
-    case MODE_G2R:
-        return launch_plane_mode<T, MODE_G2R>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
-    case MODE_R2G:
-        return launch_plane_mode<T, MODE_R2G>(g, t, L, S, V, psi, band0, threads, lds_bytes, st);
-    case MODE_DENSITY:
-        if (g.xq) return hipErrorInvalidValue; // density runs on the row-buffer x pass only
-        return launch_plane_mode<T, MODE_DENSITY>(g, t, L, S, V, psi, band0, threads, lds_bytes,
-                                                  st);
+    case MODE_APPLY: return run(std::integral_constant<int, MODE_APPLY>{});
+    case MODE_G2R: return run(std::integral_constant<int, MODE_G2R>{});
+    case MODE_R2G: return run(std::integral_constant<int, MODE_R2G>{});
+    case MODE_DENSITY: return run(std::integral_constant<int, MODE_DENSITY>{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -1804,8 +1866,25 @@ hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStrea
                        g.N3, g.L1x, g.L2x, g.L1y, g.L2y);
     return hipGetLastError();
 }
+#endif // VLOC_PART_STICK
 
-#define VLOC_INSTANTIATE(T)                                                                       \
+// The build compiles this file once per precision and part (in parallel).
+#define VLOC_PLANE_APPLY(T, F)                                                                    \
+    template hipError_t F<T, MODE_APPLY>(const Geometry &, const DevTables &, const Launch &,    \
+                                         void *, const void *, void *, int64_t, int, int,        \
+                                         hipStream_t);
+#define VLOC_PLANE_AUX(T, F)                                                                      \
+    template hipError_t F<T, MODE_G2R>(const Geometry &, const DevTables &, const Launch &,      \
+                                       void *, const void *, void *, int64_t, int, int,          \
+                                       hipStream_t);                                             \
+    template hipError_t F<T, MODE_R2G>(const Geometry &, const DevTables &, const Launch &,      \
+                                       void *, const void *, void *, int64_t, int, int,          \
+                                       hipStream_t);                                             \
+    template hipError_t F<T, MODE_DENSITY>(const Geometry &, const DevTables &, const Launch &,  \
+                                           void *, const void *, void *, int64_t, int, int,      \
+                                           hipStream_t);
+#if defined(VLOC_PART_STICK)
+#define VLOC_INSTANTIATE_STICK(T)                                                                 \
     template hipError_t launch_stick_fwd<T>(const Geometry &, const DevTables &, const Launch &, \
                                             void *, int, hipStream_t);                           \
     template hipError_t launch_stick_bwd<T>(const Geometry &, const DevTables &, const Launch &, \
@@ -1814,7 +1893,28 @@ hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStrea
                                         void *, const void *, void *, int64_t, int, int,         \
                                         hipStream_t);                                            \
     template hipError_t launch_arrange_v<T>(const Geometry &, const void *, void *, hipStream_t);
-// The build compiles this file once per precision (in parallel).
+#else
+#define VLOC_INSTANTIATE_STICK(T)
+#endif
+#if defined(VLOC_PART_FULL_APPLY)
+#define VLOC_INSTANTIATE_FULL_APPLY(T) VLOC_PLANE_APPLY(T, launch_plane_full_mode)
+#else
+#define VLOC_INSTANTIATE_FULL_APPLY(T)
+#endif
+#if defined(VLOC_PART_FULL_AUX)
+#define VLOC_INSTANTIATE_FULL_AUX(T) VLOC_PLANE_AUX(T, launch_plane_full_mode)
+#else
+#define VLOC_INSTANTIATE_FULL_AUX(T)
+#endif
+#if defined(VLOC_PART_ROWS)
+#define VLOC_INSTANTIATE_ROWS(T)                                                                  \
+    VLOC_PLANE_APPLY(T, launch_plane_rows_mode) VLOC_PLANE_AUX(T, launch_plane_rows_mode)
+#else
+#define VLOC_INSTANTIATE_ROWS(T)
+#endif
+#define VLOC_INSTANTIATE(T)                                                                       \
+    VLOC_INSTANTIATE_STICK(T) VLOC_INSTANTIATE_FULL_APPLY(T) VLOC_INSTANTIATE_FULL_AUX(T)        \
+    VLOC_INSTANTIATE_ROWS(T)
 #if !defined(VLOC_ONLY_F32)
 VLOC_INSTANTIATE(double)
 #endif

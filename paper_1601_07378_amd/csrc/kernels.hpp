@@ -24,6 +24,10 @@ struct DevTables {
     // whole-plane layout, per occupied x-plane hc and row y (hc-major, N2 per
     // hc): the slot of stick (hmin + hc, y), or -1
     const int *yslot;
+    // plane positions that lie inside an occupied x-plane's k span but hold no
+    // stick (zero in the y pass's input); rows [hole_off, hole_off + nholes)
+    // of a segment
+    const int *holes;
 };
 
 struct Geometry {
@@ -33,7 +37,6 @@ struct Geometry {
     unsigned long long nxo_magic; // ceil(2^40 / nxo): v / nxo = (v nxo_magic) >> 40, v < 2^16
     int hmin_mod;   // hmin mod N1
     int ldy, ldx, ldz;
-    int rows;       // unused (kept for layout reporting)
     int rb, rl;     // x rows per wavefront batch, padded row length in the plane kernel
     int xw;         // wavefronts taking part in the x pass
     int xq;         // > 0: quad x pass with N1 = 4 xq (no row buffer)
@@ -62,6 +65,7 @@ struct Seg {
     int slot_off, group_off, col_off; // first row in slot_info, groups, cols
     int band_lo, nb, blk_lo;
     int nbr;          // real mode: real bands from `in` / `out` (2 nb or 2 nb - 1)
+    int hole_off, nholes; // rows of the segment in the hole table
 };
 struct Launch {
     int nseg;  // segments in use (1 .. kMaxSeg)
@@ -83,6 +87,16 @@ template <typename T>
 hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, int mode, void *S,
                         const void *V, void *psi, int64_t band0, int threads, int lds_bytes,
                         hipStream_t st);
+// The plane-kernel launchers of the two layouts (whole plane in LDS; occupied
+// x-planes with row buffers or lane quads), called by launch_plane.
+template <typename T, int MODE>
+hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                                  const void *V, void *psi, int64_t band0, int threads, int lds,
+                                  hipStream_t st);
+template <typename T, int MODE>
+hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                                  const void *V, void *psi, int64_t band0, int threads, int lds,
+                                  hipStream_t st);
 // Density helpers (reduce.hip): FP64 reductions and band scaling.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
 // partial planes in [z][y][x] order, or with full != 0 in the full-plane

@@ -18,7 +18,11 @@ namespace vloc {
 
 static const double kTwoPi = 6.283185307179586476925286766559;
 
-static const int kCodelets[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16};
+// Register DFT codelets compiled in the kernels (dft_codelets.h).  Every
+// 2,3,5-smooth length up to kMaxLine is a product of two of them.
+static const int kCodelets[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32};
+static const int kNumCodelets = (int)(sizeof kCodelets / sizeof kCodelets[0]);
+static const int kMaxLine = 960;
 
 bool is_codelet(int r)
 {
@@ -31,7 +35,7 @@ bool split_length(int L, Split &s)
 {
     const int *codelets = kCodelets;
     int best1 = 0, best2 = 0;
-    for (int i = 0; i < 12; ++i) {
+    for (int i = 0; i < kNumCodelets; ++i) {
         const int a = codelets[i];
         if (L % a) continue;
         int b = L / a;
@@ -54,8 +58,6 @@ std::vector<double> twiddle_table(int L)
     for (int j = 0; j < L; ++j) {
         // angle 2 pi j / L with j already in [0, L); use symmetry so that the
         // argument of cos/sin stays in [0, pi/4]
-        long n8 = 8L * j;
-        long oct = n8 / L;
         double c, s;
         // reduce to quadrant q and residue r: angle = pi/2 (q + r/L)
         long q = (4L * j) / L, r = 4L * j - q * L;
@@ -68,7 +70,6 @@ std::vector<double> twiddle_table(int L)
             c = std::sin(b);
             s = std::cos(b);
         }
-        (void)oct;
         double cr, sr;
         switch (q) {
         case 0: cr = c; sr = s; break;
@@ -212,14 +213,22 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     for (int i = 0; i < 3; ++i) {
         p.grid[i] = grid[i];
         p.kpt[i] = k[i];
-        if (grid[i] < 1 || grid[i] > 256) {
-            err = "grid dimension outside [1, 256]";
+        if (grid[i] < 1 || grid[i] > kMaxLine) {
+            err = "grid dimension outside [1, " + std::to_string(kMaxLine) + "]";
+            return VLOC_E_GRID;
+        }
+        int r = grid[i];
+        for (int f : {2, 3, 5})
+            while (r % f == 0) r /= f;
+        if (r != 1) {
+            err = "grid dimension " + std::to_string(grid[i]) +
+                  " has a prime factor other than 2, 3 and 5";
             return VLOC_E_GRID;
         }
     }
     if (!split_length(grid[0], p.sx) || !split_length(grid[1], p.sy) ||
         !split_length(grid[2], p.sz)) {
-        err = "grid dimension is not a product of two codelet sizes {1..6,8,9,10,12,15,16}";
+        err = "internal: no two-codelet split of a 2,3,5-smooth grid dimension";
         return VLOC_E_GRID;
     }
     {
@@ -236,6 +245,13 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             sp[a]->L1 = l1;
             sp[a]->L2 = L / l1;
         }
+    }
+    // workgroups of more than 512 threads have registers for codelets of at
+    // most 16 points
+    const bool big_codelet = std::max(std::max(p.sx.L1, p.sx.L2), std::max(p.sy.L1, p.sy.L2)) > 16;
+    if (big_codelet && p.opt.plane_threads > 512) {
+        err = "plane_threads > 512 needs x and y codelets of at most 16 points";
+        return VLOC_E_INVALID;
     }
     for (int i = 0; i < 9; ++i) {
         p.cell[i] = cell[i];
@@ -533,12 +549,18 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             p.plane_rb = 0;
             p.plane_rows = 0;
             p.plane_lds = (int32_t)full_bytes;
-            p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads : (es == 16 ? 1024 : 512);
+            p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads
+                                                  : (es == 16 && !big_codelet ? 1024 : 512);
         }
     }
-    // per occupied x-plane: first k (mod N2) and number of k on sticks
+    // per occupied x-plane: first k (mod N2) and the span of k from the first
+    // to the last stick of the plane.  On a skewed cell with a k-shift the
+    // sticks of one x-plane need not be contiguous in k (the sphere's section
+    // at fixed h can miss every integer l at some k between two that it
+    // meets); those positions are holes, zero in the y pass's input.
     p.col_kmin.assign(p.nxo, 0);
     p.col_kcnt.assign(p.nxo, 0);
+    p.holes.clear();
     {
         std::vector<int32_t> kmin(p.nxo, INT32_MAX), kmax(p.nxo, INT32_MIN);
         for (const Stick &s : p.sticks) {
@@ -550,12 +572,21 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         for (const Stick &s : p.sticks) seen[s.h - p.hmin]++;
         for (int hc = 0; hc < p.nxo; ++hc) {
             if (!seen[hc]) continue;
-            if (kmax[hc] - kmin[hc] + 1 != seen[hc]) {
-                err = "internal: k range of an x-plane has holes";
-                return VLOC_E_SPHERE;
-            }
             p.col_kmin[hc] = ((kmin[hc] % grid[1]) + grid[1]) % grid[1];
-            p.col_kcnt[hc] = seen[hc];
+            p.col_kcnt[hc] = kmax[hc] - kmin[hc] + 1;
+        }
+        // sticks are in canonical (h, k) order: walk each plane's k values
+        size_t i = 0;
+        while (i < p.sticks.size()) {
+            const int32_t h = p.sticks[i].h;
+            int32_t next_k = p.sticks[i].k;
+            for (; i < p.sticks.size() && p.sticks[i].h == h; ++i) {
+                for (int32_t kk = next_k; kk < p.sticks[i].k; ++kk) {
+                    p.holes.push_back(h);
+                    p.holes.push_back(kk);
+                }
+                next_k = p.sticks[i].k + 1;
+            }
         }
     }
 

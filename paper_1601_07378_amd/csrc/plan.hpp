@@ -57,7 +57,8 @@ struct HostPlan {
     int32_t plane_rb = 0, plane_rl = 0; // x rows per wave batch, padded row length
     int32_t plane_xw = 0;               // wavefronts running the x pass
     int32_t plane_xq = 0;               // > 0: quad x pass, N1 = 4 plane_xq
-    std::vector<int32_t> col_kmin, col_kcnt; // per occupied x-plane k range
+    std::vector<int32_t> col_kmin, col_kcnt; // per occupied x-plane: first k, span of k
+    std::vector<int32_t> holes;   // (h, k) pairs inside an x-plane's k span with no stick
 
     // real (gamma) mode: coefficients of the half sphere only, two bands per
     // complex transform

@@ -47,6 +47,6 @@ int main()
 {
     srand48(7);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(8) CASE(9) CASE(10) CASE(12) CASE(15)
-    CASE(16)
+    CASE(16) CASE(18) CASE(20) CASE(24) CASE(25) CASE(27) CASE(30) CASE(32)
     return 0;
 }

@@ -15,9 +15,10 @@ C4 = synth.BATCH_WORKLOADS["c4_kpts"]
 
 
 def test_axis_splits():
-    assert at.axis_splits(96) == [6, 8, 12, 16]
-    assert at.axis_splits(72) == [6, 8, 9, 12]
-    assert at.axis_splits(128) == [8, 16]
+    assert at.axis_splits(96) == [3, 4, 6, 8, 12, 16, 24, 32]
+    assert at.axis_splits(72) == [3, 4, 6, 8, 9, 12, 18, 24]
+    assert at.axis_splits(128) == [4, 8, 16, 32]
+    assert at.axis_splits(125) == [5, 25]
     assert at.axis_splits(7) == []
     assert at.axis_splits(5) == [1, 5]
     for L in (24, 80, 96, 100, 128, 144):
@@ -54,7 +55,7 @@ def test_split_option_validation():
     lay = p.layout()
     assert (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"], lay["L1z"], lay["L2z"]) == \
         (12, 8, 6, 16, 16, 6)
-    for bad in ((7, 0, 0), (0, 5, 0), (0, 0, 32), (-2, 0, 0)):
+    for bad in ((7, 0, 0), (0, 5, 0), (0, 0, 48), (-2, 0, 0)):
         with pytest.raises(vloc.VlocError) as e:
             vloc.Plan((96, 96, 96), cell, 288.0, split=bad)
         assert e.value.status == vloc.VLOC_E_INVALID

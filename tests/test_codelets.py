@@ -29,11 +29,14 @@ def results(tmp_path_factory):
     return rows
 
 
+SIZES = [1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32]
+
+
 def test_every_codelet_size(results):
-    assert sorted(results) == [1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16]
+    assert sorted(results) == SIZES
 
 
-@pytest.mark.parametrize("R", [1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16])
+@pytest.mark.parametrize("R", SIZES)
 def test_codelet_matches_dft(results, R):
     d_minus, d_plus, f_minus, f_plus = results[R]
     assert d_minus <= 1e-15 and d_plus <= 1e-15, (R, d_minus, d_plus)

@@ -142,7 +142,8 @@ def test_finite_differences_16_directions(name, grid, cell, ecut, k, nb):
 def test_grad_128_r32_512_bands_f32_with_f64_check():
     """128^3, |G| <= 32 (137,065 PW), 512 bands: FP32 energy and gradients (FP64
     reductions) against the FP64 path on the GPU; the FP64 path against the
-    oracle on sampled bands; FD on 4 directions in FP64."""
+    oracle on sampled bands; central differences (h = 1e-4, FP64) on 16 random
+    directions in c and 16 in V, drawn on the device."""
     w_ = synth.WORKLOADS["c5_128"]
     grid, cell, ecut = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"])
     nb = w_["nbands"]
@@ -170,18 +171,22 @@ def test_grad_128_r32_512_bands_f32_with_f64_check():
     sample = [0, 255, 511]
     out = oracle.apply(grid, cell, ecut, (0, 0, 0), c[sample], V)
     assert relerr(gc64[sample], 2 * w[sample, None] * out) < 1e-12
-    # FD (FP64) on 4 random directions
+    # FD (FP64) on 16 random directions in c and 16 in V, drawn on the device
     plan, tc, tV, tw = res["f64"][3:]
-    rng = np.random.default_rng(5)
+    gc_d = tc.grad.detach()
+    gV_d = tV.grad.detach()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
     h = 1e-4
-    for i in range(4):
-        d = torch.from_numpy(rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)).cuda()
+    for i in range(16):
+        d = torch.complex(torch.randn(c.shape, generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn(c.shape, generator=gen, device="cuda", dtype=torch.float64))
         fd = (_energy(plan, tc.detach() + h * d, tV.detach(), tw.detach()) -
               _energy(plan, tc.detach() - h * d, tV.detach(), tw.detach())) / (2 * h)
-        an = float(np.sum(np.real(np.conj(gc64) * d.cpu().numpy())))
-        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
-        u = torch.from_numpy(rng.standard_normal(V.shape)).cuda()
+        an = torch.sum(torch.real(torch.conj(gc_d) * d)).item()
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (i, fd, an)
+        u = torch.randn(V.shape, generator=gen, device="cuda", dtype=torch.float64)
         fdv = (_energy(plan, tc.detach(), tV.detach() + h * u, tw.detach()) -
                _energy(plan, tc.detach(), tV.detach() - h * u, tw.detach())) / (2 * h)
-        anv = float(np.dot(gV64, u.cpu().numpy().ravel()))
-        assert abs(fdv - anv) <= 1e-7 * max(1.0, abs(anv))
+        anv = torch.sum(gV_d * u).item()
+        assert abs(fdv - anv) <= 1e-7 * max(1.0, abs(anv)), (i, fdv, anv)

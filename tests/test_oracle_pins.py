@@ -131,6 +131,40 @@ def test_greedy_deal_invariants(ngroups):
             assert np.all(np.diff(counts[order]) <= 0)
 
 
+# Balance of the 96^3 / R = 24 sphere's 1,793 sticks dealt to 64 and 256 groups,
+# (max, min) plane waves per group: integers counted independently (by brute
+# force over the sphere, then the deal rules of Sec. 3.2 read as stable sort by
+# descending count, cyclic / snake / canonical-order deal).
+BALANCE_PINS = {
+    (64, "cyclic"): (929, 880), (64, "snake"): (910, 894), (64, "unsorted"): (965, 852),
+    (256, "cyclic"): (250, 201), (256, "snake"): (231, 217), (256, "unsorted"): (257, 191),
+}
+
+
+@pytest.mark.parametrize("ngroups,mode", sorted(BALANCE_PINS))
+def test_greedy_deal_balance_pins_96(ngroups, mode):
+    st = oracle.sticks(oracle.sphere_py(synth.cubic_cell(), 288.0))
+    g, _ = oracle.greedy_deal(st[:, 3], ngroups, mode)
+    loads = oracle.group_loads(st[:, 3], g, ngroups)
+    assert (int(loads.max()), int(loads.min())) == BALANCE_PINS[(ngroups, mode)]
+    assert loads.sum() == 57777
+
+
+@pytest.mark.parametrize("cell", [SKEW, SKEW * np.array([[1.0], [0.6], [0.7]]),
+                                  np.array([[4.38, 1.0686, -2.8831], [2.3836, 8.7056, -0.1596],
+                                            [-2.339, 2.8047, 3.0992]])])
+def test_reciprocal_basis_duality(cell):
+    """a_i . b_j = 2 pi delta_ij (eq. 3's G = h b1 + k b2 + l b3), checked as dot
+    products of the rows, not by inverting again."""
+    B = oracle.reciprocal(cell)
+    for i in range(3):
+        for j in range(3):
+            d = float(np.dot(cell[i], B[j]))
+            assert abs(d - (2 * math.pi if i == j else 0.0)) < 1e-13, (i, j, d)
+    # the volume relation det(B) = (2 pi)^3 / det(A)
+    assert abs(np.linalg.det(B) * np.linalg.det(cell) - (2 * math.pi) ** 3) < 1e-9
+
+
 # --------------------------------------------------------- dense brute force
 
 TINY = [((4, 4, 4), 1.0), ((6, 6, 6), 1.0), ((8, 8, 8), 2.0), ((10, 10, 10), 2.0),

@@ -18,6 +18,12 @@ from conftest import ROOT, gpu_available
 vloc = pytest.importorskip("paper_1601_07378_amd.vloc")
 
 SKEW = np.array([[6.0, 0.3, -0.2], [0.5, 7.0, 0.4], [-0.3, 0.6, 6.5]])
+# Strongly skewed cells with a k-shift (cell, Ecut, k): on some x-planes the
+# sphere's sticks skip a k value (the section at fixed (h, k) holds no integer l)
+HOLE_A = (np.array([[4.38, 1.0686, -2.8831], [2.3836, 8.7056, -0.1596], [-2.339, 2.8047, 3.0992]]),
+          39.588, (-0.3216, -0.2485, -0.2091))
+HOLE_B = (np.array([[3.7123, -1.7955, 2.7501], [-0.9051, 5.5968, 2.7584],
+                    [2.9182, 1.8833, 5.3089]]), 37.086, (-0.229, 0.1557, -0.141))
 
 
 def test_library_exports_every_declared_symbol():
@@ -40,6 +46,13 @@ CASES = [
     ((72, 96, 128), synth.cubic_cell(), 162.0, (0.25, 0.25, 0.25)),
     ((16, 18, 20), SKEW, 12.0, (0.25, 1 / 3, 0.0)),
     ((15, 9, 10), SKEW * np.array([[1.0], [0.6], [0.7]]), 5.0, (0.1, -0.2, 0.3)),
+    # skewed cells with a k-shift whose x-planes have holes in their k span
+    ((16, 30, 15), HOLE_A[0], HOLE_A[1], HOLE_A[2]),
+    ((15, 18, 18), HOLE_B[0], HOLE_B[1], HOLE_B[2]),
+    # lengths that need codelets above 16 points, and a z axis above 256
+    ((125, 24, 24), np.diag([5.0, 1.0, 1.0]) * 2 * np.pi, 18.0, (0, 0, 0)),
+    ((250, 27, 25), np.diag([10.0, 1.0, 1.0]) * 2 * np.pi, 18.0, (0.1, 0, 0)),
+    ((24, 24, 288), np.diag([1.0, 1.0, 12.0]) * 2 * np.pi, 18.0, (0, 0, 0)),
 ]
 
 
@@ -60,6 +73,21 @@ def test_stick_map_matches_oracle(grid, cell, ecut, k):
     ps = vloc.Plan(grid, cell, ecut, k, deal="snake")
     gs_ref, _ = oracle.greedy_deal(st_ref[:, 3], ng, "snake")
     assert np.array_equal(ps.stick_groups(), gs_ref)
+
+
+@pytest.mark.parametrize("cell,ecut,k,grid,nholes", [(*HOLE_A, (16, 30, 15), 1),
+                                                     (*HOLE_B, (15, 18, 18), 7)])
+def test_planes_with_k_holes_are_accepted(cell, ecut, k, grid, nholes):
+    """An x-plane's sticks need not be contiguous in k on a skewed cell; the
+    plan accepts such spheres (the oracle's enumeration shows the holes)."""
+    st = oracle.sticks(oracle.sphere_py(cell, ecut, k))
+    holes = 0
+    for h in np.unique(st[:, 0]):
+        ks = st[st[:, 0] == h, 1]
+        holes += (ks.max() - ks.min() + 1) - ks.size
+    assert holes == nholes
+    p = vloc.Plan(grid, cell, ecut, k)
+    assert np.array_equal(p.sticks().astype(np.int64), st)
 
 
 def test_known_counts():
@@ -92,17 +120,50 @@ def _create(grid, cell=None, ecut=18.0, k=(0, 0, 0), opt=None):
     return s, h
 
 
+def _smooth(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
 @pytest.mark.parametrize("grid,status", [((7, 24, 24), vloc.VLOC_E_GRID),
                                          ((14, 24, 24), vloc.VLOC_E_GRID),
-                                         ((250, 24, 24), vloc.VLOC_E_GRID),
-                                         ((257, 24, 24), vloc.VLOC_E_GRID),
+                                         ((24, 21, 24), vloc.VLOC_E_GRID),
+                                         ((24, 24, 22), vloc.VLOC_E_GRID),
+                                         ((961, 24, 24), vloc.VLOC_E_GRID),
+                                         ((972, 24, 24), vloc.VLOC_E_GRID),
                                          ((0, 24, 24), vloc.VLOC_E_GRID),
+                                         ((125, 24, 24), vloc.VLOC_OK),
+                                         ((243, 24, 24), vloc.VLOC_OK),
+                                         ((250, 24, 24), vloc.VLOC_OK),
+                                         ((24, 24, 960), vloc.VLOC_OK),
                                          ((24, 24, 24), vloc.VLOC_OK)])
 def test_grid_validation(grid, status):
     s, h = _create(grid)
     assert s == status
     assert (h.value is None) == (status != vloc.VLOC_OK)
     vloc.lib().vloc_plan_destroy(h)
+
+
+def test_every_smooth_length_accepted():
+    """Every 2,3,5-smooth length up to 960 is accepted on each axis, every other
+    length is refused with VLOC_E_GRID (the sphere is kept small)."""
+    for n in range(1, 961):
+        for axis in range(3):
+            grid = [24, 24, 24]
+            grid[axis] = n
+            s, h = _create(tuple(grid), ecut=0.3)
+            vloc.lib().vloc_plan_destroy(h)
+            assert s == (vloc.VLOC_OK if _smooth(n) else vloc.VLOC_E_GRID), (grid, s)
+
+
+def test_big_codelets_need_512_threads():
+    s, h = _create((125, 24, 24), opt=vloc.make_options(plane_threads=1024))
+    assert s == vloc.VLOC_E_INVALID
+    p = vloc.Plan((125, 24, 24), synth.cubic_cell(), 18.0)
+    assert p.layout()["plane_threads"] <= 512
+    assert max(p.layout()["L1x"], p.layout()["L2x"]) == 25
 
 
 def test_sphere_and_cell_validation():

@@ -148,6 +148,25 @@ vloc_status vloc_set_stream(vloc_plan plan, void *hip_stream);
  * allocated on first use; calls on one plan must not run concurrently. */
 vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void *V, void *out);
 
+/* Allocation-free variant of vloc_apply, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, result and stream ordering as
+ * vloc_apply (bitwise the same output), but the kernels' scratch (the
+ * potential in the plane kernel's order and the stick buffer) lives in one
+ * static device array of 64 MiB per GPU, held until the process ends, and the
+ * call makes no hipMalloc, hipFree or other allocation.  Preconditions, each
+ * refused with VLOC_E_INVALID and a message: the plan's tables are already on
+ * the device (its first vloc_apply call uploads them), the current device is
+ * the plan's, and one band fits: N1 N2 N3 real values (whole-plane layouts)
+ * plus N3 nsticks complex values at most 64 MiB (bands then run in chunks of
+ * as many as fit).  The scratch needs no clearing (every call writes all of
+ * it before reading it).  Every call on one GPU shares that GPU's array, from
+ * any plan: calls that overlap on one GPU (other streams, other threads)
+ * race and give wrong results; order them on one stream.  Timing
+ * (vloc_plan_enable_timing) is not recorded on this path. */
+vloc_status vloc_apply_noalloc(vloc_plan plan, const void *c, int64_t nbands, const void *V,
+                               void *out);
+
 /* ---------------------------------------------------------------- queries */
 /* Host outputs, caller-allocated.  npw and gvectors describe the
  * coefficients of one band in the caller's arrays (the half sphere for a

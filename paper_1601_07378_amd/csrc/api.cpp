@@ -8,9 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -71,6 +73,12 @@ struct vloc_batch_s {
     std::vector<uintptr_t> graph_key;
     int64_t graphs_captured = 0, graph_launches = 0;
 };
+
+// Scratch of vloc_apply_noalloc: the potential in the plane kernel's order,
+// then the stick buffer of one band chunk.  Each GPU the library runs on holds
+// its own copy until the process ends, and every call on that GPU shares it.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -389,6 +397,33 @@ struct Part {
     int nb;
 };
 
+// Segment of member `member` for its launch bands [b0, b0 + nb): caller data
+// pointers of its first band, its stick-buffer offset and its table rows.  In
+// the real mode a launch band is a pair of the caller's bands.
+void fill_seg(const Engine &E, int member, const void *in, void *out, int64_t nbands, int64_t b0,
+              int nb, long long s_off, int band_lo, int blk_lo, Seg &s)
+{
+    const HostPlan &m = *E.members[member];
+    const size_t es = (size_t)m.elem_bytes();
+    const int64_t per = m.gamma ? 2 : 1; // caller bands per launch band
+    const int64_t first = per * b0;      // first caller band of the segment
+    s.in = in ? static_cast<const char *>(in) + first * m.npw_io() * es : nullptr;
+    s.out = out ? static_cast<char *>(out) + first * m.npw_io() * es : nullptr;
+    s.nbr = (int)std::min<int64_t>(per * nb, nbands - first);
+    s.s_off = s_off;
+    s.nst = (int)m.nst();
+    s.npw = (int)m.npw_io();
+    s.ngroups = m.ngroups;
+    s.slot_off = E.slot_off[member];
+    s.group_off = E.group_off[member];
+    s.col_off = E.col_off[member];
+    s.hole_off = E.hole_off[member];
+    s.nholes = E.nholes[member];
+    s.band_lo = band_lo;
+    s.nb = nb;
+    s.blk_lo = blk_lo;
+}
+
 // The launches of one call: the caller's bands of every member, concatenated
 // in member order, cut into chunks of at most `chunk` bands; a chunk holds one
 // segment per member it touches.  In the real mode a launch band is a pair of
@@ -410,27 +445,9 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
         int band_lo = 0, blk_lo = 0;
         for (size_t i = 0; i < cur.size(); ++i) {
             const Part &p = cur[i];
+            fill_seg(E, p.member, in ? in[p.member] : nullptr, out ? out[p.member] : nullptr,
+                     nbands[p.member], p.b0, p.nb, s_off, band_lo, blk_lo, L.seg[i]);
             const HostPlan &m = *E.members[p.member];
-            const size_t es = (size_t)m.elem_bytes();
-            const int64_t per = m.gamma ? 2 : 1; // caller bands per launch band
-            const int64_t first = per * p.b0;    // first caller band of the segment
-            Seg &s = L.seg[i];
-            s.in = in ? static_cast<const char *>(in[p.member]) + first * m.npw_io() * es
-                      : nullptr;
-            s.out = out ? static_cast<char *>(out[p.member]) + first * m.npw_io() * es : nullptr;
-            s.nbr = (int)std::min<int64_t>(per * p.nb, nbands[p.member] - first);
-            s.s_off = s_off;
-            s.nst = (int)m.nst();
-            s.npw = (int)m.npw_io();
-            s.ngroups = m.ngroups;
-            s.slot_off = E.slot_off[p.member];
-            s.group_off = E.group_off[p.member];
-            s.col_off = E.col_off[p.member];
-            s.hole_off = E.hole_off[p.member];
-            s.nholes = E.nholes[p.member];
-            s.band_lo = band_lo;
-            s.nb = p.nb;
-            s.blk_lo = blk_lo;
             s_off += (long long)p.nb * N3 * m.nst();
             band_lo += p.nb;
             blk_lo += p.nb * m.ngroups;
@@ -461,8 +478,9 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
 // V; G2R / R2G / DENSITY (one member) take psi / weights indexed from the
 // launch's first band.
 template <typename T>
-vloc_status run_launches(Engine &E, int mode, const std::vector<Launch> &ls, const void *V,
-                         void *psi, const double *wts, hipStream_t st, bool timed)
+vloc_status run_launches(Engine &E, int mode, const Launch *ls, size_t nl, const void *V,
+                         void *psi, const double *wts, hipStream_t st, bool timed, void *S,
+                         void *VT, bool arrange = true)
 {
     const HostPlan &h = *E.members[0];
     const Geometry &g = E.geo;
@@ -470,13 +488,15 @@ vloc_status run_launches(Engine &E, int mode, const std::vector<Launch> &ls, con
     t.wts = wts;
     hipError_t e;
     int64_t band0 = 0;
-    if (mode == MODE_APPLY && g.full && !ls.empty()) {
-        // the potential in the full-plane kernel's order, once per call
-        if ((e = launch_arrange_v<T>(g, V, E.d_VT, st)) != hipSuccess)
+    if (mode == MODE_APPLY && g.full && nl > 0) {
+        // the potential in the full-plane kernel's order, once per call (with
+        // arrange false, VT already holds it)
+        if (arrange && (e = launch_arrange_v<T>(g, V, VT, st)) != hipSuccess)
             return hip_fail(e, "potential arrangement launch");
-        V = E.d_VT;
+        V = VT;
     }
-    for (const Launch &L : ls) {
+    for (size_t li = 0; li < nl; ++li) {
+        const Launch &L = ls[li];
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         if (timed) {
             if ((e = next_events(E, ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -484,15 +504,15 @@ vloc_status run_launches(Engine &E, int mode, const std::vector<Launch> &ls, con
             (void)hipEventRecord(ev[0], st);
         }
         if (mode != MODE_R2G) {
-            e = launch_stick_fwd<T>(g, t, L, E.d_S, h.stick_threads, st);
+            e = launch_stick_fwd<T>(g, t, L, S, h.stick_threads, st);
             if (e != hipSuccess) return hip_fail(e, "stick forward launch");
         }
         if (timed) (void)hipEventRecord(ev[1], st);
-        e = launch_plane<T>(g, t, L, mode, E.d_S, V, psi, band0, h.plane_threads, h.plane_lds, st);
+        e = launch_plane<T>(g, t, L, mode, S, V, psi, band0, h.plane_threads, h.plane_lds, st);
         if (e != hipSuccess) return hip_fail(e, "plane launch");
         if (timed) (void)hipEventRecord(ev[2], st);
         if (mode != MODE_G2R && mode != MODE_DENSITY) {
-            e = launch_stick_bwd<T>(g, t, L, E.d_S, h.stick_threads, st);
+            e = launch_stick_bwd<T>(g, t, L, S, h.stick_threads, st);
             if (e != hipSuccess) return hip_fail(e, "stick backward launch");
         }
         if (timed) (void)hipEventRecord(ev[3], st);
@@ -519,8 +539,10 @@ vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, cons
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
     void *psi = mode == MODE_G2R ? out : (mode == MODE_R2G ? const_cast<void *>(in) : nullptr);
     if (p->hp.opt.precision == VLOC_F32)
-        return run_launches<float>(E, mode, ls, V, psi, wts, E.stream, E.timing);
-    return run_launches<double>(E, mode, ls, V, psi, wts, E.stream, E.timing);
+        return run_launches<float>(E, mode, ls.data(), ls.size(), V, psi, wts, E.stream, E.timing,
+                                   E.d_S, E.d_VT);
+    return run_launches<double>(E, mode, ls.data(), ls.size(), V, psi, wts, E.stream, E.timing,
+                                E.d_S, E.d_VT);
 }
 
 vloc_status read_timing(Engine &E, double ms[3], int64_t launches[3])
@@ -547,6 +569,26 @@ vloc_status read_timing(Engine &E, double ms[3], int64_t launches[3])
     E.rec_modes.clear();
     if (ms) std::memcpy(ms, acc, sizeof acc);
     if (launches) std::memcpy(launches, cnt, sizeof cnt);
+    return VLOC_OK;
+}
+
+// Device address of `scratch` on each GPU, looked up once per device with that
+// device current (in host code the array's name is only a stand-in for it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+vloc_status scratch_address(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(VLOC_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
     return VLOC_OK;
 }
 
@@ -624,6 +666,69 @@ vloc_status vloc_apply(vloc_plan plan, const void *c, int64_t nbands, const void
     if (((uintptr_t)c | (uintptr_t)out) % es || (uintptr_t)V % (es / 2))
         return fail(VLOC_E_INVALID, "misaligned c, V or out");
     return dispatch(plan, MODE_APPLY, c, nbands, V, out);
+}
+
+vloc_status vloc_apply_noalloc(vloc_plan plan, const void *c, int64_t nbands, const void *V,
+                               void *out)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!c || !V || !out) return fail(VLOC_E_INVALID, "NULL c, V or out");
+    const HostPlan &h = plan->hp;
+    Engine &E = plan->eng;
+    const size_t es = (size_t)h.elem_bytes();
+    const size_t cbytes = (size_t)nbands * (size_t)h.npw_io() * es;
+    const size_t nvox = (size_t)h.grid[0] * h.grid[1] * h.grid[2];
+    if (overlaps(out, cbytes, c, cbytes) || overlaps(out, cbytes, V, nvox * (es / 2)))
+        return fail(VLOC_E_ALIAS, "out overlaps c or V");
+    if (((uintptr_t)c | (uintptr_t)out) % es || (uintptr_t)V % (es / 2))
+        return fail(VLOC_E_INVALID, "misaligned c, V or out");
+    // the arranged potential, then the stick buffer of as many bands as fit
+    const size_t vt = h.plane_full ? (nvox * (es / 2) + 255) / 256 * 256 : 0;
+    const size_t per_band = (size_t)h.grid[2] * (size_t)h.nst() * es;
+    if (vt + per_band > kScratchBytes) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "one band needs %zu bytes of scratch (potential %zu + stick buffer %zu); "
+                      "the allocation-free path has %zu",
+                      vt + per_band, vt, per_band, kScratchBytes);
+        return fail(VLOC_E_INVALID, buf);
+    }
+    if (!E.uploaded)
+        return fail(VLOC_E_INVALID, "the plan's tables are not on the device yet (they are "
+                                    "uploaded by its first vloc_apply call)");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != E.device) return fail(VLOC_E_INVALID, "the current device is not the plan's");
+    void *base = nullptr;
+    vloc_status s = scratch_address(dev, &base);
+    if (s != VLOC_OK) return s;
+    void *VT = base;
+    void *S = static_cast<char *>(base) + vt;
+    // equal chunks of at most this many launch bands, as vloc_apply cuts them
+    const int64_t cap = std::min<int64_t>(h.band_chunk, (int64_t)((kScratchBytes - vt) / per_band));
+    const int64_t units = h.gamma ? (nbands + 1) / 2 : nbands;
+    const int64_t nch = (units + cap - 1) / cap;
+    const int64_t chunk = (units + nch - 1) / nch;
+    const bool f32 = h.opt.precision == VLOC_F32;
+    for (int64_t b0 = 0, i = 0; b0 < units; b0 += chunk, ++i) {
+        Launch L{};
+        const int nb = (int)std::min<int64_t>(chunk, units - b0);
+        L.nseg = 1;
+        fill_seg(E, 0, c, out, nbands, b0, nb, 0, 0, 0, L.seg[0]);
+        L.nbt = nb;
+        L.nblk = nb * h.ngroups;
+        // the first chunk arranges the potential into VT (whole-plane layout);
+        // the later ones read it from there
+        s = f32 ? run_launches<float>(E, MODE_APPLY, &L, 1, V, nullptr, nullptr, E.stream, false,
+                                      S, VT, i == 0)
+                : run_launches<double>(E, MODE_APPLY, &L, 1, V, nullptr, nullptr, E.stream, false,
+                                       S, VT, i == 0);
+        if (s != VLOC_OK) return s;
+    }
+    return VLOC_OK;
 }
 
 vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r)
@@ -999,9 +1104,10 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
     const bool f32 = h0.opt.precision == VLOC_F32;
     if (!batch->use_graph) {
-        return f32 ? run_launches<float>(E, MODE_APPLY, ls, V, nullptr, nullptr, E.stream, E.timing)
-                   : run_launches<double>(E, MODE_APPLY, ls, V, nullptr, nullptr, E.stream,
-                                          E.timing);
+        return f32 ? run_launches<float>(E, MODE_APPLY, ls.data(), ls.size(), V, nullptr, nullptr,
+                                         E.stream, E.timing, E.d_S, E.d_VT)
+                   : run_launches<double>(E, MODE_APPLY, ls.data(), ls.size(), V, nullptr,
+                                          nullptr, E.stream, E.timing, E.d_S, E.d_VT);
     }
     // graph path: capture the launches once per set of pointers and counts
     std::vector<uintptr_t> key;
@@ -1025,10 +1131,10 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
         if ((e = hipStreamBeginCapture(batch->cap_stream, hipStreamCaptureModeRelaxed)) !=
             hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        s = f32 ? run_launches<float>(E, MODE_APPLY, ls, V, nullptr, nullptr, batch->cap_stream,
-                                      false)
-                : run_launches<double>(E, MODE_APPLY, ls, V, nullptr, nullptr, batch->cap_stream,
-                                       false);
+        s = f32 ? run_launches<float>(E, MODE_APPLY, ls.data(), ls.size(), V, nullptr, nullptr,
+                                      batch->cap_stream, false, E.d_S, E.d_VT)
+                : run_launches<double>(E, MODE_APPLY, ls.data(), ls.size(), V, nullptr, nullptr,
+                                       batch->cap_stream, false, E.d_S, E.d_VT);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(batch->cap_stream, &g);
         if (s != VLOC_OK) {

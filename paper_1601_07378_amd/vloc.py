@@ -36,7 +36,7 @@ EXPORTS = [
     "vloc_band_dot", "vloc_weighted_sum", "vloc_density", "vloc_scale_bands",
     "vloc_batch_create", "vloc_batch_destroy", "vloc_batch_plan", "vloc_batch_set_stream",
     "vloc_batch_apply", "vloc_batch_use_graph", "vloc_batch_enable_timing",
-    "vloc_batch_read_timing", "vloc_batch_info",
+    "vloc_batch_read_timing", "vloc_batch_info", "vloc_apply_noalloc",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
         "vloc_plan_destroy": [vp],
         "vloc_set_stream": [vp, vp],
         "vloc_apply": [vp, vp, i64, vp, vp],
+        "vloc_apply_noalloc": [vp, vp, i64, vp, vp],
         "vloc_plan_npw": [vp, i64p],
         "vloc_plan_gvectors": [vp, i32p],
         "vloc_plan_sticks": [vp, i64p, i32p],
@@ -259,6 +260,23 @@ class Plan:
         self.set_stream(stream)
         check(lib().vloc_apply(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
                                ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def apply_noalloc(self, c, V, out, stream=None):
+        """As apply, through the allocation-free entry point (static device
+        scratch; the plan must have run one apply first); `out` is required."""
+        ct, rt = self._dtypes()
+        for t, dt in ((c, ct), (out, ct), (V, rt)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"expected contiguous device tensors of {ct} / {rt}")
+        if c.dim() != 2 or c.shape[1] != self.npw or out.shape != c.shape:
+            raise ValueError("c and out must be (nbands, npw)")
+        if V.numel() != self.grid[0] * self.grid[1] * self.grid[2]:
+            raise ValueError("V must hold N3*N2*N1 values")
+        self.set_stream(stream)
+        check(lib().vloc_apply_noalloc(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
+                                       ctypes.c_void_p(V.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr())))
         return out
 
     # ---- energy and gradient pieces (FP64 reductions)

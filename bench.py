@@ -5,7 +5,13 @@ the |G| <= 24 sphere (57,777 plane waves, 1,793 z-sticks), K1 -> K2 -> K3 per
 band chunk.  Inputs are synthetic (seeded), resident in HBM before timing.
 Prints one JSON line on stdout; details go to stderr.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision f64]
+Timing: every throughput figure comes from a timed region with no per-launch
+events (HIP events only at its two ends).  The per-kernel split and the
+roofline of the dominant kernel come from a second timed region of the same
+steps in which the library records HIP events around each of its launches on
+the plan's stream.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
 from __future__ import annotations
 
@@ -22,8 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
-FP64_PEAK = 78.6e12        # FLOP/s vector FP64
-FP32_PEAK_NONPACKED = 78.6e12  # FLOP/s FP32 without packed instructions
+VECTOR_PEAK = 78.6e12      # FLOP/s: FP64 vector; FP32 without packed instructions runs the same
 
 
 def log(*a):
@@ -38,10 +43,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(precision: str, nbands: int):
+def read_traffic(precision: str, nbands_per_launch: float):
     """HBM bytes per plane-kernel launch from the committed counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"vloc_apply_96cubed_256bands_{precision}.txt")
+    path = os.path.join(ROOT, "profiles", f"k2_plane_96cubed_{precision}_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -52,7 +57,7 @@ def read_traffic(precision: str, nbands: int):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_band"]) * nbands
+        return float(kv["hbm_bytes_per_band"]) * nbands_per_launch
     except (KeyError, ValueError):
         return None
 
@@ -74,15 +79,31 @@ def workload_sizes(plan, grid, nbands, precision):
     return dict(nst=nst, npw=npw, nxo=nxo, N=N, s=s, sv=sv, b_alg=b_alg, f_alg=f_alg)
 
 
-def measure(precision, steps, warmup, chunk=0, timing=True, gamma=False):
+def timed_region(run, steps, stream):
+    """ms over `steps` calls of run(), HIP events at the two ends only."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, keep=False):
+    """Throughput of one plan on a named workload; optionally a second pass with
+    per-launch events for the kernel split."""
     import torch
 
     import synth
     from paper_1601_07378_amd import vloc
 
-    w = synth.WORKLOADS["c2_96"]
+    w = synth.WORKLOADS[workload]
     grid, cell, ecut, nb = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"]), w["nbands"]
-    plan = vloc.Plan(grid, cell, ecut, precision=precision, band_chunk=chunk, gamma=gamma)
+    plan = vloc.Plan(grid, cell, ecut, precision=precision, gamma=gamma)
     hkl = plan.gvectors()
     ct, rt = (torch.complex128, torch.float64) if precision == "f64" else (torch.complex64, torch.float32)
     c = torch.from_numpy(synth.coefficients(hkl, nb)).to("cuda", ct)
@@ -90,29 +111,52 @@ def measure(precision, steps, warmup, chunk=0, timing=True, gamma=False):
     out = torch.empty_like(c)
     stream = torch.cuda.current_stream()
     plan.set_stream(stream)
-    for _ in range(warmup):
+
+    def run():
         plan.apply(c, V, out=out, stream=stream)
-    torch.cuda.synchronize()
-    if timing:
+
+    for _ in range(warmup):
+        run()
+    ms = timed_region(run, steps, stream)
+    res = dict(plan=plan, grid=grid, nb=nb, ms_step=ms / steps, bands_per_s=nb * steps / (ms / 1e3),
+               sizes=workload_sizes(plan, grid, nb, precision), layout=plan.layout())
+    if kernel_pass:
         plan.enable_timing(True)
         plan.read_timing()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
-        plan.apply(c, V, out=out, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    kms, kn = plan.read_timing() if timing else ([0, 0, 0], [0, 0, 0])
-    sizes = workload_sizes(plan, grid, nb, precision)
-    lay = plan.layout()
-    bal = plan.balance()
-    return dict(plan=plan, grid=grid, nb=nb, ms_total=ms_total, wall=wall, kms=kms, kn=kn,
-                sizes=sizes, layout=lay, balance=bal, out=out, c=c, V=V)
+        ms_k = timed_region(run, steps, stream)
+        kms, kn = plan.read_timing()
+        plan.enable_timing(False)
+        res.update(ms_step_kernel_pass=ms_k / steps, kms=kms, kn=kn)
+    if keep:
+        res.update(out=out, c=c, V=V)
+    return res
+
+
+def balance_report(workload):
+    """Plane waves per stick group (the analogue of the paper's Tab. 2 statistic,
+    per workgroup instead of per process) for the greedy deal (the paper's rule,
+    Sec. 3.2), the snake variant and the unsorted cyclic deal it improves on, at
+    the plan's group count; and the grid-sufficiency flag N_i >= 4 R_i (Sec.
+    3.1: the product V psi is band-limited to twice the sphere's radius)."""
+    import synth
+    from paper_1601_07378_amd import vloc
+
+    w = synth.WORKLOADS[workload]
+    grid, cell, ecut = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"])
+    out = {}
+    for deal in ("greedy", "snake", "unsorted"):
+        b = vloc.Plan(grid, cell, ecut, deal=deal).balance()
+        out[deal] = {"max": int(b.max()), "min": int(b.min()), "mean": round(float(b.mean()), 2),
+                     "max_over_mean": round(float(b.max() / b.mean()), 4)}
+    p = vloc.Plan(grid, cell, ecut)
+    out["groups"] = int(p.balance().size)
+    out["sticks"] = int(p.sticks().shape[0])
+    hkl = p.gvectors()
+    # 2 R_i = the sphere's extent along axis i minus one
+    two_r = [int(x) for x in hkl.max(0) - hkl.min(0)]
+    out["grid_check"] = {"N": list(grid), "four_R": [2 * t for t in two_r],
+                         "N_ge_4R": [bool(n >= 2 * t) for n, t in zip(grid, two_r)]}
+    return out
 
 
 SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
@@ -120,9 +164,9 @@ SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
 
 def measure_batch(steps, warmup):
     """Several k-points with uneven spheres and band counts (72x96x128, R = 18,
-    4 k-points, 64/128/256/512 bands): FP32 batch replayed from a HIP graph with
-    the tuned schedule, against the plain FP64 path (one plan per k-point, one
-    apply after another) and the FP64 batch."""
+    4 k-points, 64/128/256/512 bands): the batch (one launch per kernel per
+    chunk) against plain per-k plans applied one after another, in FP32 (graph
+    replay, tuned schedule) and FP64."""
     import torch
 
     import synth
@@ -141,24 +185,11 @@ def measure_batch(steps, warmup):
             tuned, source = entry["best"], "autotuned (paper_1601_07378_amd/schedules.json)"
     res = {}
     stream = torch.cuda.current_stream()
-
-    def timed(run):
-        for _ in range(warmup):
-            run()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            run()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    for prec, opts, graph, name in (("f32", autotune.to_options(tuned) if tuned else {}, True,
-                                     "f32_batch_graph"),
-                                    ("f64", {}, False, "f64_batch"),
-                                    ("f64", {}, False, "f64_plain")):
+    legs = (("f32", autotune.to_options(tuned) if tuned else {}, True, "f32_batch_graph"),
+            ("f32", {}, False, "f32_plain"),
+            ("f64", {}, False, "f64_batch"),
+            ("f64", {}, False, "f64_plain"))
+    for prec, opts, graph, name in legs:
         ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
             (torch.complex64, torch.float32)
         b = vloc.Batch(grid, cell, ecut, kpts, precision=prec, **opts)
@@ -166,7 +197,7 @@ def measure_batch(steps, warmup):
               for i, (p, nb, k) in enumerate(zip(b.plans, nbs, kpts))]
         outs = [torch.empty_like(c) for c in cs]
         V = torch.from_numpy(synth.potential(grid, w["ngauss"])).to("cuda", rt)
-        if name == "f64_plain":
+        if name.endswith("plain"):
             plans = [vloc.Plan(grid, cell, ecut, k, precision=prec) for k in kpts]
             for p in plans:
                 p.set_stream(stream)
@@ -181,16 +212,22 @@ def measure_batch(steps, warmup):
 
             def run():
                 b.apply(cs, V, outs=outs, stream=stream)
-        ms = timed(run)
+        for _ in range(warmup):
+            run()
+        ms = timed_region(run, steps, stream) / steps
         res[name] = {"value": round(total / (ms / 1e3), 1), "ms_per_apply": round(ms, 4)}
         del b, cs, outs, V
         torch.cuda.empty_cache()
-    res["speedup_f32_graph_vs_f64_plain"] = round(res["f32_batch_graph"]["value"] /
+    res["speedup_f32_batch_vs_f32_plain"] = round(res["f32_batch_graph"]["value"] /
+                                                  res["f32_plain"]["value"], 3)
+    res["speedup_f64_batch_vs_f64_plain"] = round(res["f64_batch"]["value"] /
+                                                  res["f64_plain"]["value"], 3)
+    res["speedup_f32_batch_vs_f64_plain"] = round(res["f32_batch_graph"]["value"] /
                                                   res["f64_plain"]["value"], 3)
     res["unit"] = "bands/s"
     res["workload"] = ("72x96x128 grid, |g+k| <= 18, k = (0,0,0), (1/4,0,0), (1/4,1/4,0), "
                        "(1/4,1/4,1/4) with 64/128/256/512 bands (960 per apply)")
-    res["schedule"] = tuned or "planner default"
+    res["schedule_f32_batch"] = tuned or "planner default"
     res["schedule_source"] = source
     return res
 
@@ -228,15 +265,7 @@ def measure_grad(steps, warmup):
 
         for _ in range(warmup):
             step()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+        ms = timed_region(step, steps, stream) / steps
         res[prec] = {"value": round(nb / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
                      "plane_xmode": plan.layout()["plane_xmode"]}
         del c, V, w, plan
@@ -247,7 +276,7 @@ def measure_grad(steps, warmup):
     return res
 
 
-def cpu_baseline(nbands_sample: int):
+def cpu_baseline(nbands_sample: int, threads: int):
     import oracle
     import synth
 
@@ -256,7 +285,6 @@ def cpu_baseline(nbands_sample: int):
     hkl = oracle.sphere_py(cell, ecut)
     c = synth.coefficients(hkl, w["nbands"])[:nbands_sample]
     V = synth.potential(grid, w["ngauss"])
-    threads = oracle.max_threads()
     t0 = time.perf_counter()
     oracle.apply(grid, cell, ecut, (0, 0, 0), c, V, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -265,19 +293,47 @@ def cpu_baseline(nbands_sample: int):
                        f"FP64, full-cube unpruned FFTs, OpenMP over bands; {dt:.1f} s")
 
 
+def path_figures(r, precision):
+    sz = r["sizes"]
+    v = r["bands_per_s"]
+    return {"value": round(v, 1), "ms_per_step": round(r["ms_step"], 4),
+            "hbm_frac_path": round(sz["b_alg"] * v / HBM_PEAK, 4),
+            "flop_rate_tflops": round(sz["f_alg"] * v / 1e12, 2),
+            "algorithmic_bytes_per_band": round(sz["b_alg"])}
+
+
+def kernel_figures(r, steps):
+    """Per-kernel split and the roofline of the plane kernel K2 from the
+    per-launch event pass."""
+    sz = r["sizes"]
+    kms, kn = r["kms"], r["kn"]
+    N3 = r["grid"][2]
+    # plane kernel: S read and written for its bands, plus the arranged
+    # potential once per launch
+    b_k2_band = 2 * sz["nst"] * N3 * sz["s"]
+    launch_bands = r["nb"] * steps / kn[1]
+    k2_launch_bytes = b_k2_band * launch_bands + sz["N"] * sz["sv"]
+    k2_avg_s = kms[1] / kn[1] / 1e3
+    achieved = k2_launch_bytes / k2_avg_s
+    split = {"k1_stick_fwd": round(kms[0] / steps, 4), "k2_plane": round(kms[1] / steps, 4),
+             "k3_stick_bwd": round(kms[2] / steps, 4),
+             "launches_per_step": [n // steps for n in kn],
+             "ms_per_step_with_events": round(r["ms_step_kernel_pass"], 4)}
+    return split, achieved, k2_launch_bytes, launch_bands, k2_avg_s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample-1thread", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f32", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-gamma", action="store_true")
-    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the 96^3 FP64 and FP32 legs only (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the M0, real-mode, batch and gradient legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of 256 MiB so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -293,65 +349,50 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     log(f"# device: {torch.cuda.get_device_name(0)}")
-    r = measure(args.precision, args.steps, args.warmup, args.chunk)
+    steps, warmup = args.steps, args.warmup
+
+    # ---- headline: 96^3, 256 bands, FP64
+    r = measure("c2_96", "f64", steps, warmup, keep=True)
+    head = path_figures(r, "f64")
+    split, achieved, k2_bytes, launch_bands, k2_avg_s = kernel_figures(r, steps)
+    log(f"# f64: {r['ms_step']:.4f} ms/step ({r['ms_step_kernel_pass']:.4f} with per-launch "
+        f"events), {r['bands_per_s']:,.0f} bands/s, {head['hbm_frac_path'] * 100:.1f}% of HBM "
+        f"peak; K1 {split['k1_stick_fwd']:.4f} K2 {split['k2_plane']:.4f} K3 "
+        f"{split['k3_stick_bwd']:.4f} ms/step; K2 {k2_avg_s * 1e3:.4f} ms/launch; "
+        f"layout {r['layout']}")
     sz = r["sizes"]
-    nb = r["nb"]
-    ms_step = r["ms_total"] / args.steps
-    bands_per_s = nb * args.steps / (r["ms_total"] / 1e3)
-    kms, kn = r["kms"], r["kn"]
-    chunk = r["layout"]["band_chunk"]
-    # plane kernel (dominant): bytes per launch = S read + S written for its
-    # bands + V once
-    N3 = r["grid"][2]
-    b_k2_band = 2 * sz["nst"] * N3 * sz["s"]
-    k2_bytes = b_k2_band * nb * args.steps + sz["N"] * sz["sv"] * kn[1]
-    k2_time = kms[1] / 1e3
-    achieved = k2_bytes / k2_time if k2_time > 0 else None
-    log(f"# {args.precision}: {ms_step:.3f} ms/step, {bands_per_s:,.0f} bands/s; kernels ms/step "
-        f"K1 {kms[0] / args.steps:.3f} K2 {kms[1] / args.steps:.3f} K3 {kms[2] / args.steps:.3f}; "
-        f"launches {kn}; layout {r['layout']}")
-    path_frac = sz["b_alg"] * bands_per_s / HBM_PEAK
-    flop_rate = sz["f_alg"] * bands_per_s
-    bal = r["balance"]
-    log(f"# path: B_alg/band {sz['b_alg']:.0f} B -> {path_frac * 100:.1f}% of HBM peak; "
-        f"F_alg/band {sz['f_alg']:.3e} -> {flop_rate / 1e12:.1f} TFLOP/s; group PW max/min/mean "
-        f"{bal.max()}/{bal.min()}/{bal.mean():.1f}")
-    k2_launch_bytes = k2_bytes / kn[1] if kn[1] else None
-    # bands per launch: a call is cut into equal chunks of at most band_chunk
-    launch_bands = nb * args.steps / kn[1] if kn[1] else chunk
-    traffic = read_traffic(args.precision, launch_bands)
     result = {
         "metric": "band V_loc|psi> applications/sec at 96^3 (FP64 vs FP32) + % HBM peak",
-        "value": round(bands_per_s, 1),
+        "value": head["value"],
         "unit": "bands/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": "f64",
         "data": "synthetic (seeded Gaussian coefficients scaled by 1/(1+|G|^2); V = 0.5 + 32 Gaussians)",
         "config": {"workload": "96^3 grid, |G|<=24 sphere (57777 PW, 1793 sticks), 256 bands, Gamma, "
-                               "cubic cell", "grid": list(r["grid"]), "nbands": nb,
-                   "npw": sz["npw"], "band_chunk_max": chunk,
-                   "bands_per_launch": round(launch_bands, 2), "precision": args.precision},
-        "hbm_frac_path": round(path_frac, 4),
+                               "cubic cell", "grid": list(r["grid"]), "nbands": r["nb"],
+                   "npw": sz["npw"], "band_chunk_max": r["layout"]["band_chunk"],
+                   "bands_per_launch": round(launch_bands, 2), "precision": "f64"},
+        "hbm_frac_path": head["hbm_frac_path"],
+        "flop_rate_tflops": head["flop_rate_tflops"],
         "roofline": {"bound": "hbm", "kernel": "k_plane (K2)",
-                     "achieved": round(achieved / 1e9, 1) if achieved else None,
-                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_launch": round(k2_launch_bytes) if k2_launch_bytes else None,
-                     "avg_launch_ms": round(kms[1] / kn[1], 4) if kn[1] else None},
-        "kernel_ms_per_step": {"k1_stick_fwd": round(kms[0] / args.steps, 4),
-                               "k2_plane": round(kms[1] / args.steps, 4),
-                               "k3_stick_bwd": round(kms[2] / args.steps, 4)},
+                     "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": read_traffic("f64", launch_bands),
+                     "algorithmic_bytes_per_launch": round(k2_bytes),
+                     "avg_launch_ms": round(k2_avg_s * 1e3, 4),
+                     "timing": "per-launch HIP events on the plan stream, second timed region of "
+                               "the same steps",
+                     "measured_limiter": "LDS traffic and VALU issue (SQ counters in profiles/)"},
+        "kernel_ms_per_step": split,
     }
-    # FP64 band energies e_n = Re<c_n|V c_n> (FP64 reductions), kept to check FP32
-    e64 = r["plan"].band_dot(r["c"], r["out"]) if args.precision == "f64" else None
-    out64 = r["out"] if args.precision == "f64" else None
+    e64 = r["plan"].band_dot(r["c"], r["out"])
+    out64 = r["out"]
     del r
     torch.cuda.empty_cache()
     if args.copy_calibration:
@@ -362,57 +403,81 @@ def main():
         torch.cuda.synchronize()
         log("# copy calibration: 268435456 B read + 268435456 B written")
         del src, dst
-    if not args.no_f32 and args.precision == "f64":
-        r32 = measure("f32", args.steps, args.warmup, args.chunk, timing=False)
-        v32 = r32["nb"] * args.steps / (r32["ms_total"] / 1e3)
-        result["f32"] = {"value": round(v32, 1), "ms_per_step": round(r32["ms_total"] / args.steps, 4),
-                         "speedup_vs_f64": round(v32 / bands_per_s, 3),
-                         "hbm_frac_path": round(r32["sizes"]["b_alg"] * v32 / HBM_PEAK, 4)}
-        # accuracy of the FP32 path against the FP64 path (itself within 1e-12 of
-        # the oracle in the parity tests), every band of the workload; the FP32
-        # band energies use the FP64 reductions
-        o32 = r32["out"].to(torch.complex128)
-        rel = (torch.linalg.vector_norm(o32 - out64, dim=1) /
-               torch.linalg.vector_norm(out64, dim=1))
-        e32 = r32["plan"].band_dot(r32["c"], r32["out"])
-        erel = ((e32 - e64).abs() / e64.abs()).max().item()
-        result["f32"]["max_rel_err_per_band_vs_f64"] = float(f"{rel.max().item():.3e}")
-        result["f32"]["max_rel_err_band_energy_vs_f64"] = float(f"{erel:.3e}")
-        log(f"# f32: {v32:,.0f} bands/s ({v32 / bands_per_s:.2f}x f64); max per-band rel err "
-            f"{rel.max().item():.2e}, band-energy rel err {erel:.2e}")
-        del r32, o32
-    if not args.no_gamma and args.precision == "f64":
+
+    # ---- the metric's FP32 column, timed the same way
+    r32 = measure("c2_96", "f32", steps, warmup, keep=True)
+    f32 = path_figures(r32, "f32")
+    s32, a32, b32, lb32, k2s32 = kernel_figures(r32, steps)
+    f32["speedup_vs_f64"] = round(r32["bands_per_s"] / head["value"], 3)
+    f32["kernel_ms_per_step"] = s32
+    f32["k2_roofline"] = {"achieved_GBps": round(a32 / 1e9, 1), "frac": round(a32 / HBM_PEAK, 4),
+                          "avg_launch_ms": round(k2s32 * 1e3, 4),
+                          "algorithmic_bytes_per_launch": round(b32),
+                          "traffic": read_traffic("f32", lb32)}
+    # accuracy of the FP32 path against the FP64 path (itself within 1e-12 of the
+    # oracle in the parity tests), every band; the band energies use the FP64
+    # reductions
+    o32 = r32["out"].to(torch.complex128)
+    rel = (torch.linalg.vector_norm(o32 - out64, dim=1) / torch.linalg.vector_norm(out64, dim=1))
+    e32 = r32["plan"].band_dot(r32["c"], r32["out"])
+    erel = ((e32 - e64).abs() / e64.abs()).max().item()
+    f32["max_rel_err_per_band_vs_f64"] = float(f"{rel.max().item():.3e}")
+    f32["max_rel_err_band_energy_vs_f64"] = float(f"{erel:.3e}")
+    result["f32"] = f32
+    log(f"# f32: {r32['bands_per_s']:,.0f} bands/s ({f32['speedup_vs_f64']:.2f}x f64), "
+        f"{f32['hbm_frac_path'] * 100:.1f}% of HBM peak; K2 {k2s32 * 1e3:.4f} ms/launch; max "
+        f"per-band rel err {rel.max().item():.2e}, band-energy rel err {erel:.2e}")
+    del r32, o32, out64
+    torch.cuda.empty_cache()
+    result["balance"] = balance_report("c2_96")
+    log(f"# balance: {result['balance']}")
+
+    if not args.only_headline and not args.no_extra:
+        # the paper's workload shape (80^3 grid, ~35k plane waves, 1001 bands)
+        m0 = {}
+        for prec in ("f64", "f32"):
+            rm = measure("m0_80", prec, max(3, steps // 4), warmup, kernel_pass=False)
+            m0[prec] = path_figures(rm, prec)
+            del rm
+        m0["workload"] = ("80^3 grid, |G|^2 <= 413 sphere (35273 PW), 1001 bands, Gamma, cubic "
+                          "cell: the shape of the paper's 80^3 / 35160-PW / 1001-state workload")
+        m0["unit"] = "bands/s"
+        result["m0_paper_shape"] = m0
+        log(f"# m0 80^3 x 1001: f64 {m0['f64']['value']:,.0f} bands/s "
+            f"({m0['f64']['hbm_frac_path'] * 100:.1f}%), f32 {m0['f32']['value']:,.0f}")
         # the paper's real mode (Gamma point, half sphere, two bands per transform)
         # on the same grid and sphere: a different input class (real psi), so it
         # is reported beside the complex-path value, not as it
         gm = {}
         for prec in ("f64", "f32"):
-            rg = measure(prec, args.steps, args.warmup, args.chunk, timing=False, gamma=True)
-            vg = rg["nb"] * args.steps / (rg["ms_total"] / 1e3)
-            gm[prec] = {"value": round(vg, 1), "ms_per_step": round(rg["ms_total"] / args.steps, 4)}
+            rg = measure("c2_96", prec, steps, warmup, gamma=True, kernel_pass=False)
+            gm[prec] = {"value": round(rg["bands_per_s"], 1), "ms_per_step": round(rg["ms_step"], 4)}
             del rg
         gm["unit"] = "bands/s"
-        gm["speedup_f64_vs_complex_f64"] = round(gm["f64"]["value"] / bands_per_s, 3)
+        gm["speedup_f64_vs_complex_f64"] = round(gm["f64"]["value"] / head["value"], 3)
         gm["workload"] = ("96^3, |G|<=24, 256 real bands (half sphere 28889 coefficients per "
                           "band), two bands per complex transform")
         result["gamma_real_mode"] = gm
         log(f"# gamma real mode: f64 {gm['f64']['value']:,.0f} bands/s, "
             f"f32 {gm['f32']['value']:,.0f} bands/s")
-    if not args.no_batch and args.precision == "f64":
-        rb = measure_batch(args.steps, args.warmup)
+        rb = measure_batch(steps, warmup)
         result["batched_kpoints"] = rb
-        log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} bands/s, f64 batch "
-            f"{rb['f64_batch']['value']:,.0f}, f64 plain {rb['f64_plain']['value']:,.0f} "
-            f"({rb['schedule_source']})")
-    if not args.no_grad and args.precision == "f64":
-        rg = measure_grad(max(2, args.steps // 4), 1)
+        log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} vs f32 plain "
+            f"{rb['f32_plain']['value']:,.0f}; f64 batch {rb['f64_batch']['value']:,.0f} vs f64 "
+            f"plain {rb['f64_plain']['value']:,.0f} bands/s ({rb['schedule_source']})")
+        rg = measure_grad(max(2, steps // 4), 1)
         result["differentiable_energy"] = rg
         log(f"# energy + gradients 128^3 x 512: f32 {rg['f32']['value']:,.0f} bands/s, "
             f"f64 {rg['f64']['value']:,.0f} bands/s")
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(args.cpu_sample)
+        import oracle
+        cb = cpu_baseline(args.cpu_sample, oracle.max_threads())
         result["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()}
         log(f"# cpu oracle: {cb['value']:.2f} bands/s on {cb['cores']} threads")
+        c1 = cpu_baseline(args.cpu_sample_1thread, 1)
+        result["cpu_baseline_1thread"] = {k: (round(v, 3) if isinstance(v, float) else v)
+                                          for k, v in c1.items()}
+        log(f"# cpu oracle, 1 thread: {c1['value']:.3f} bands/s")
     print(json.dumps(result), flush=True)
 
 

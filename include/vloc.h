@@ -66,9 +66,15 @@ typedef enum { VLOC_F64 = 0, VLOC_F32 = 1 } vloc_precision;
 /* Deal of z-sticks (columns meeting the sphere) to stick groups; each group is
  * one workgroup of the two stick-transform kernels.  GREEDY is the paper's
  * rule (sort by descending plane-wave count, ties in canonical order, deal in
- * turn; Sec. 3.2); SNAKE reverses every other pass; CONTIGUOUS keeps canonical
- * order (no balancing). */
-typedef enum { VLOC_DEAL_GREEDY = 0, VLOC_DEAL_SNAKE = 1, VLOC_DEAL_CONTIGUOUS = 2 } vloc_deal;
+ * turn; Sec. 3.2); SNAKE reverses every other pass; CONTIGUOUS cuts the
+ * canonical order into consecutive runs; UNSORTED deals the canonical order in
+ * turn without sorting (the baseline the paper's balancing improves on). */
+typedef enum {
+    VLOC_DEAL_GREEDY = 0,
+    VLOC_DEAL_SNAKE = 1,
+    VLOC_DEAL_CONTIGUOUS = 2,
+    VLOC_DEAL_UNSORTED = 3
+} vloc_deal;
 
 /* Zero-initialised options mean: F64, greedy deal, automatic sizes. */
 typedef struct {
@@ -240,12 +246,15 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
 
 /* ------------------------------------------------------------- batches */
 /* Several k-points of one crystal (same grid, cell, ecut and options, each
- * with its own cutoff sphere and band count) applied together: the bands of
- * all k-points are concatenated (k-point order) and each band chunk runs as
- * ONE launch of each kernel, whose workgroups take planes and stick groups of
- * every k-point from one work list (the paper's balancing of uneven units,
- * Sec. 3.2, carried to whole k-points; Sec. 1 on aggregating the transforms
- * of many bands).  The members share one plane layout: each covers the union
+ * with its own cutoff sphere and band count) applied together (the paper's
+ * balancing of uneven units, Sec. 3.2, carried to whole k-points; Sec. 1 on
+ * aggregating the transforms of many bands).  A k-point with at least half a
+ * band chunk of bands fills the device by itself and runs in launches of its
+ * own (its bands cut into equal chunks); the bands of the smaller k-points are
+ * concatenated (k-point order) and each chunk of them runs as ONE launch of
+ * each kernel, whose workgroups take planes and stick groups of every k-point
+ * in it from one work list.  All launches of a call are stream-ordered and can
+ * be replayed as one HIP graph (vloc_batch_use_graph).  The members share one plane layout: each covers the union
  * of the k-points' occupied x-planes, so a member's own results equal those
  * of a stand-alone plan of the same k. */
 typedef struct vloc_batch_s *vloc_batch; /* opaque; owned by the library */

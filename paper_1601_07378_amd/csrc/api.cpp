@@ -426,10 +426,16 @@ void fill_seg(const Engine &E, int member, const void *in, void *out, int64_t nb
 
 // The launches of one call: the caller's bands of every member, concatenated
 // in member order, cut into chunks of at most `chunk` bands; a chunk holds one
-// segment per member it touches.  In the real mode a launch band is a pair of
-// the caller's bands.  Returns the stick-buffer bytes of the largest chunk.
+// segment per member it touches.  With own > 0, a member of at least `own`
+// launch bands instead gets launches of its own (its bands cut into equal
+// chunks of at most `chunk`), and only the smaller members share launches: a
+// launch of one segment runs the plane kernel's direct y form, and a member
+// that large fills the device by itself.  In the real mode a launch band is a
+// pair of the caller's bands.  Returns the stick-buffer bytes of the largest
+// chunk.
 size_t make_launches(const Engine &E, const void *const *in, void *const *out,
-                     const int64_t *nbands, int64_t chunk, std::vector<Launch> &ls)
+                     const int64_t *nbands, int64_t chunk, std::vector<Launch> &ls,
+                     int64_t own = 0, int64_t own_cap = 0)
 {
     ls.clear();
     const int nm = (int)E.members.size();
@@ -437,7 +443,8 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
     size_t need = 0;
     std::vector<Part> cur;
     int64_t cur_bands = 0;
-    auto flush = [&]() {
+    std::vector<Part> solo;
+    auto emit = [&](std::vector<Part> &cur) {
         if (cur.empty()) return;
         Launch L{};
         L.nseg = (int)cur.size();
@@ -457,10 +464,22 @@ size_t make_launches(const Engine &E, const void *const *in, void *const *out,
         need = std::max(need, (size_t)s_off * (size_t)E.members[0]->elem_bytes());
         ls.push_back(L);
         cur.clear();
+    };
+    auto flush = [&]() {
+        emit(cur);
         cur_bands = 0;
     };
     for (int m = 0; m < nm; ++m) {
         const int64_t units = E.members[m]->gamma ? (nbands[m] + 1) / 2 : nbands[m];
+        if (own > 0 && units >= own) {
+            const int64_t nch = (units + own_cap - 1) / own_cap;
+            const int64_t each = (units + nch - 1) / nch;
+            for (int64_t b = 0; b < units; b += each) {
+                solo.push_back(Part{m, b, (int)std::min(each, units - b)});
+                emit(solo);
+            }
+            continue;
+        }
         int64_t b = 0;
         while (b < units) {
             int64_t take = std::min(units - b, chunk - cur_bands);
@@ -1097,10 +1116,16 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
     }
     cmax = std::min<int64_t>(cmax, INT32_MAX / maxg);
     cmax = std::min<int64_t>(cmax, INT32_MAX / h0.grid[2]);
-    const int64_t nch = (total + cmax - 1) / cmax;
-    const int64_t chunk = (total + nch - 1) / nch;
+    // k-points of at least half a chunk get launches of their own; the others
+    // share launches, cut into equal chunks
+    const int64_t own = (cmax + 1) / 2;
+    int64_t shared = 0;
+    for (int i = 0; i < nk; ++i)
+        if (nbands[i] < own) shared += nbands[i];
+    const int64_t nch = std::max<int64_t>(1, (shared + cmax - 1) / cmax);
+    const int64_t chunk = std::max<int64_t>(1, (shared + nch - 1) / nch);
     std::vector<Launch> ls;
-    size_t need = make_launches(E, c, out, nbands, chunk, ls);
+    size_t need = make_launches(E, c, out, nbands, chunk, ls, own, cmax);
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
     const bool f32 = h0.opt.precision == VLOC_F32;
     if (!batch->use_graph) {

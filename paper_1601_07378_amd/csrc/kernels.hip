@@ -1539,6 +1539,266 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
         g, t, L, S, VT, psi, band0);
 }
 
+// ------------------------------------------------------- K2, row blocks
+// Row-block form of the whole-plane kernel (application, launches of one
+// segment, y pass in the direct form).  After y stage A, the L2y-point stage-B
+// transforms of index k1 touch only the rows at positions [L2y k1, L2y k1 + L2y)
+// of the transposed row order, and so do the x transforms of those rows, the
+// potential, the reverse x transforms and the reverse y stage B'.  One
+// wavefront runs that whole chain for one such block of rows, with wavefront
+// ordering only between its stages; the workgroup synchronises twice per
+// plane, after y stage A (which writes every block) and before y stage A'
+// (which reads every block).  The wavefronts of a plane then no longer move
+// through the stages in step, so the LDS traffic of one overlaps the
+// arithmetic of another.
+// The column stride is N2 + 7 complex values (7 mod 16): lanes along columns
+// (y stages) and lanes along eight rows of two neighbouring columns (x stages)
+// then fall on distinct LDS banks but for one pair.
+constexpr int kRowBlockPad = 7;
+
+template <int N1, int N2>
+__host__ __device__ constexpr int rowblock_lds_elems()
+{
+    return N1 * (N2 + kRowBlockPad) + N1 + N2;
+}
+
+template <typename T, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_plane_rowblock(Geometry g, DevTables t, Launch L,
+                                                         cx<T> *__restrict__ S,
+                                                         const T *__restrict__ VT)
+{
+    constexpr int L1x = CX1, L2x = CX2, L1y = CY1, L2y = CY2;
+    constexpr int N1 = L1x * L2x, N2 = L1y * L2y, ldy = N2 + kRowBlockPad;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *plane = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *twy = plane + N1 * ldy; // stage twiddles of y and x, [n2][k1]
+    cx<T> *twx = twy + N2;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int nxo = g.nxo, hx = g.hmin_mod;
+    for (int i = tid; i < N2; i += nthr) twy[i] = reinterpret_cast<const cx<T> *>(t.twy)[i];
+    for (int i = tid; i < N1; i += nthr) twx[i] = reinterpret_cast<const cx<T> *>(t.twx)[i];
+    const Seg sg = L.seg[0];
+    const int nb = L.nbt;
+    auto col_of = [&](int hc) {
+        int x = hx + hc;
+        return x >= N1 ? x - N1 : x;
+    };
+    auto occupied = [&](int x) {
+        int r = x - hx;
+        if (r < 0) r += N1;
+        return r < nxo;
+    };
+    // persistent XCD-aware schedule over the planes j = z nb + band (as in the
+    // other plane kernels)
+    const int total = nb * g.N3;
+    int j0 = blockIdx.x, jstep = gridDim.x, jend = total;
+    if ((gridDim.x & 7) == 0 && (total & 7) == 0) {
+        const int share = total >> 3, xcd = blockIdx.x & 7;
+        j0 = xcd * share + (blockIdx.x >> 3);
+        jstep = gridDim.x >> 3;
+        jend = (xcd + 1) * share;
+    }
+    // The thread's y stage-A task (occupied column yhc, n2 = yn2; the launcher
+    // guarantees nxo L2y <= threads) and the slots of its inputs in S, the same
+    // for every plane
+    const bool ymine = tid < nxo * L2y;
+    const int yn2 = (int)(((unsigned long long)(unsigned)tid * g.nxo_magic) >> 40);
+    const int yhc = tid - yn2 * nxo;
+    int pos[L1y];
+    cx<T> pre[L1y];
+#pragma unroll
+    for (int n1 = 0; n1 < L1y; ++n1) {
+        pos[n1] = -1;
+        pre[n1] = mk<T>(T(0), T(0));
+    }
+    if (ymine) {
+        const int *ys = t.yslot + (long long)(sg.col_off + yhc) * N2 + yn2;
+#pragma unroll
+        for (int n1 = 0; n1 < L1y; ++n1)
+            if (!masked<ZY>(n1)) pos[n1] = ys[L2y * n1];
+    }
+    auto prefetch = [&](int jj) {
+        const int zz = jj / nb, bb = jj - zz * nb;
+        const cx<T> *Sj = S + sg.s_off + ((long long)bb * g.N3 + zz) * sg.nst;
+#pragma unroll
+        for (int n1 = 0; n1 < L1y; ++n1)
+            if (!masked<ZY>(n1)) pre[n1] = pos[n1] >= 0 ? Sj[pos[n1]] : mk<T>(T(0), T(0));
+    };
+    // y stage A from the prefetched stick values (zero where no stick)
+    auto y_stage_a = [&]() {
+        cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+        T xr[L1y], xi[L1y];
+#pragma unroll
+        for (int n1 = 0; n1 < L1y; ++n1) {
+            xr[n1] = pre[n1].x;
+            xi[n1] = pre[n1].y;
+        }
+        Dft<L1y, -1, T>::run(xr, xi);
+        twiddle_pw<L1y, -1, T>(xr, xi, yn2, twy);
+#pragma unroll
+        for (int k1 = 0; k1 < L1y; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
+    };
+    // y stage A', stick positions stored straight to the plane's slice of S
+    auto y_stage_a2 = [&](cx<T> *Sd) {
+        cx<T> *col = plane + col_of(yhc) * ldy + yn2;
+        T xr[L1y], xi[L1y];
+#pragma unroll
+        for (int k1 = 0; k1 < L1y; ++k1) {
+            cx<T> v = col[L2y * k1];
+            xr[k1] = v.x;
+            xi[k1] = v.y;
+        }
+        twiddle_pw<L1y, +1, T>(xr, xi, yn2, twy);
+        Dft<L1y, +1, T>::run(xr, xi);
+#pragma unroll
+        for (int n1 = 0; n1 < L1y; ++n1)
+            if (!masked<ZY>(n1) && pos[n1] >= 0) Sd[pos[n1]] = mk<T>(xr[n1], xi[n1]);
+    };
+    __syncthreads(); // twiddles in LDS
+    if (ymine && j0 < jend) prefetch(j0);
+    cx<T> *Sprev = nullptr;
+    for (int jc = j0; jc < jend; jc += jstep) {
+        const int z = jc / nb, bl = jc - z * nb;
+        cx<T> *Sz = S + sg.s_off + ((long long)bl * g.N3 + z) * sg.nst;
+        const T *VTz = VT + (long long)z * N1 * N2;
+        // y stage A' of the previous plane and y stage A of this one: the
+        // thread's own positions of its column
+        if (ymine) {
+            if (Sprev) y_stage_a2(Sprev);
+            y_stage_a();
+        }
+        __syncthreads();
+        const bool more = jc + jstep < jend;
+        bool fetched = false;
+        for (int jb = wave; jb < L1y; jb += nwaves) {
+            const int yp0 = L2y * jb;
+            constexpr int NBT = L2y * L1x; // x stage-B tasks of the block
+            constexpr int RB = (NBT + 63) / 64;
+            // y stage B (lanes along occupied columns)
+            for (int hc = lane; hc < nxo; hc += 64) {
+                cx<T> *col = plane + col_of(hc) * ldy + yp0;
+                T xr[L2y], xi[L2y];
+#pragma unroll
+                for (int n2 = 0; n2 < L2y; ++n2) {
+                    cx<T> v = col[n2];
+                    xr[n2] = v.x;
+                    xi[n2] = v.y;
+                }
+                Dft<L2y, -1, T>::run(xr, xi);
+#pragma unroll
+                for (int k2 = 0; k2 < L2y; ++k2) col[k2] = mk<T>(xr[k2], xi[k2]);
+            }
+            wave_sync();
+            // x stage A of the block's rows (r = u mod L2y, n2 = u / L2y)
+            for (int u = lane; u < L2y * L2x; u += 64) {
+                const int r = u % L2y, n2 = u / L2y;
+                cx<T> *row = plane + n2 * ldy + yp0 + r;
+                T xr[L1x], xi[L1x];
+#pragma unroll
+                for (int n1 = 0; n1 < L1x; ++n1) {
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (!masked<ZX>(n1)) {
+                        const cx<T> w = row[L2x * n1 * ldy];
+                        if (masked<FX>(n1) || occupied(n2 + L2x * n1)) v = w;
+                    }
+                    xr[n1] = v.x;
+                    xi[n1] = v.y;
+                }
+                Dft<L1x, -1, T>::run(xr, xi);
+                twiddle_pw<L1x, -1, T>(xr, xi, n2, twx);
+#pragma unroll
+                for (int k1 = 0; k1 < L1x; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
+            }
+            wave_sync();
+            // x stage B, the potential, reverse stage B (tasks r = u mod L2y, k1 = u /
+            // L2y); the potential of every round is loaded first
+            T vv[RB][L2x];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const int u = lane + 64 * rr;
+                if (u < NBT) {
+                    const int r = u % L2y, k1 = u / L2y;
+                    const T *vrun = VTz + ((long long)k1 * N2 + yp0 + r) * L2x;
+#pragma unroll
+                    for (int k2 = 0; k2 < L2x; ++k2) vv[rr][k2] = vrun[k2];
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const int u = lane + 64 * rr;
+                if (u < NBT) {
+                    const int r = u % L2y, k1 = u / L2y;
+                    cx<T> *row = plane + L2x * k1 * ldy + yp0 + r;
+                    T xr[L2x], xi[L2x];
+#pragma unroll
+                    for (int n2 = 0; n2 < L2x; ++n2) {
+                        cx<T> v = row[n2 * ldy];
+                        xr[n2] = v.x;
+                        xi[n2] = v.y;
+                    }
+                    Dft<L2x, -1, T>::run(xr, xi);
+#pragma unroll
+                    for (int k2 = 0; k2 < L2x; ++k2) {
+                        xr[k2] *= vv[rr][k2];
+                        xi[k2] *= vv[rr][k2];
+                    }
+                    Dft<L2x, +1, T>::run(xr, xi);
+#pragma unroll
+                    for (int n2 = 0; n2 < L2x; ++n2) row[n2 * ldy] = mk<T>(xr[n2], xi[n2]);
+                }
+            }
+            wave_sync();
+            // the next plane's stick values: issued after the potential's loads,
+            // they complete behind the rest of the plane
+            if (!fetched) {
+                fetched = true;
+                if (ymine && more) prefetch(jc + jstep);
+            }
+            // x stage A', occupied outputs only
+            for (int u = lane; u < L2y * L2x; u += 64) {
+                const int r = u % L2y, n2 = u / L2y;
+                cx<T> *row = plane + n2 * ldy + yp0 + r;
+                T xr[L1x], xi[L1x];
+#pragma unroll
+                for (int k1 = 0; k1 < L1x; ++k1) {
+                    cx<T> v = row[L2x * k1 * ldy];
+                    xr[k1] = v.x;
+                    xi[k1] = v.y;
+                }
+                twiddle_pw<L1x, +1, T>(xr, xi, n2, twx);
+                Dft<L1x, +1, T>::run(xr, xi);
+#pragma unroll
+                for (int n1 = 0; n1 < L1x; ++n1) {
+                    if (masked<ZX>(n1)) continue;
+                    if (masked<FX>(n1) || occupied(n2 + L2x * n1))
+                        row[L2x * n1 * ldy] = mk<T>(xr[n1], xi[n1]);
+                }
+            }
+            wave_sync();
+            // y stage B' (lanes along occupied columns)
+            for (int hc = lane; hc < nxo; hc += 64) {
+                cx<T> *col = plane + col_of(hc) * ldy + yp0;
+                T xr[L2y], xi[L2y];
+#pragma unroll
+                for (int k2 = 0; k2 < L2y; ++k2) {
+                    cx<T> v = col[k2];
+                    xr[k2] = v.x;
+                    xi[k2] = v.y;
+                }
+                Dft<L2y, +1, T>::run(xr, xi);
+#pragma unroll
+                for (int n2 = 0; n2 < L2y; ++n2) col[n2] = mk<T>(xr[n2], xi[n2]);
+            }
+            wave_sync();
+        }
+        if (!fetched && ymine && more) prefetch(jc + jstep);
+        __syncthreads();
+        Sprev = Sz;
+    }
+    if (ymine && Sprev) y_stage_a2(Sprev);
+}
+
 // VT[z][k1][yp][k2] = V[z][y][x] with x = k1 + L1x k2 and yp = L2y (y mod L1y)
 // + y / L1y: the potential in the order the full-plane kernel's x stage B
 // reads it (each task's L2x values contiguous, tasks along yp adjacent).
@@ -1807,6 +2067,35 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
     return pick(std::false_type{});
 }
 
+// Row-block kernel: compiled splits and zero masks (a specialisation serves
+// every plan whose masks contain its own); false where none applies.
+template <typename T>
+static bool launch_plane_rowblock(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                                  const void *VT, int threads, hipStream_t st, hipError_t &err)
+{
+    if (L.nseg != 1 || threads != 768 || g.nxo * g.L2y > threads) return false;
+    auto go = [&](auto kern, int elems) {
+        const size_t lds = (size_t)elems * sizeof(cx<T>);
+        err = allow_lds(kern, lds);
+        if (err != hipSuccess) return true;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), lds, st, g, t, L,
+                           reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(VT));
+        err = hipGetLastError();
+        return true;
+    };
+#define VLOC_ROWBLOCK_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                             \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
+        (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                                   \
+        return go(k_plane_rowblock<T, X1, X2, Y1, Y2, ZX, FX, ZY, 768>,                            \
+                  rowblock_lds_elems<X1 * X2, Y1 * Y2>());
+    if constexpr (std::is_same<T, double>::value) {
+        VLOC_ROWBLOCK_CASE(12, 8, 12, 8, 0x1F0, 0xE07, 0x1F0)
+        VLOC_ROWBLOCK_CASE(12, 8, 12, 8, 0, 0, 0)
+    }
+#undef VLOC_ROWBLOCK_CASE
+    return false;
+}
+
 // Whole-plane layout.  Specialised line splits for the common grids; any
 // other split runs the same kernel with runtime sizes.
 template <typename T, int MODE>
@@ -1814,6 +2103,10 @@ hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const L
                                   const void *V, void *psi, int64_t band0, int threads, int lds,
                                   hipStream_t st)
 {
+    if constexpr (MODE == MODE_APPLY) {
+        hipError_t err = hipSuccess;
+        if (g.full == 3 && launch_plane_rowblock<T>(g, t, L, S, V, threads, st, err)) return err;
+    }
 #define VLOC_FULL_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                 \
     if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
         (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                                   \

@@ -189,7 +189,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         err = "precision must be VLOC_F64 or VLOC_F32";
         return VLOC_E_INVALID;
     }
-    if (p.opt.deal < 0 || p.opt.deal > 2) {
+    if (p.opt.deal < 0 || p.opt.deal > 3) {
         err = "unknown deal mode";
         return VLOC_E_INVALID;
     }
@@ -198,11 +198,11 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
         (p.opt.plane_threads > 512 && p.opt.precision != VLOC_F64) ||
         p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
-        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 4 || p.opt.gamma < 0 ||
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 5 || p.opt.gamma < 0 ||
         p.opt.gamma > 1) {
         err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64 "
               "(FP64: up to 1024), "
-              "plane_xwaves <= plane_threads / 64, plane_xmode 0..4, gamma 0..1)";
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..5, gamma 0..1)";
         return VLOC_E_INVALID;
     }
     p.gamma = p.opt.gamma != 0;
@@ -230,6 +230,22 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         !split_length(grid[2], p.sz)) {
         err = "internal: no two-codelet split of a 2,3,5-smooth grid dimension";
         return VLOC_E_GRID;
+    }
+    // Row-block layout of the plane kernel: blocks of L2y = 8 rows and an x
+    // split with L2x = 8 (the compiled kernels)
+    if (p.opt.plane_xmode == 5) {
+        Split *sp[2] = {&p.sx, &p.sy};
+        for (int a = 0; a < 2; ++a) {
+            if (p.opt.split[a]) continue;
+            const int L = grid[a];
+            if (L % 8 || !is_codelet(L / 8)) {
+                err = "the row-block layout (plane_xmode 5) needs N1 and N2 = 8 L1 with L1 a "
+                      "codelet length";
+                return VLOC_E_INVALID;
+            }
+            sp[a]->L1 = L / 8;
+            sp[a]->L2 = 8;
+        }
     }
     {
         Split *sp[3] = {&p.sx, &p.sy, &p.sz};
@@ -413,7 +429,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     // ---- deal (Sec. 3.2): sort by descending count, ties in canonical order
     std::vector<int32_t> order(nunits);
     std::iota(order.begin(), order.end(), 0);
-    if (p.opt.deal != VLOC_DEAL_CONTIGUOUS)
+    if (p.opt.deal == VLOC_DEAL_GREEDY || p.opt.deal == VLOC_DEAL_SNAKE)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
             return p.sticks[units[a][0]].count > p.sticks[units[b][0]].count;
         });
@@ -542,7 +558,29 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             err = "the full plane does not fit in LDS (plane_xmode 3 or 4)";
             return VLOC_E_INVALID;
         }
-        if (fits && (p.opt.plane_xmode >= 3 || p.opt.plane_xmode == 0)) {
+        if (p.opt.plane_xmode == 5) {
+            // row blocks: column stride N2 + 7, one 768-thread workgroup per CU
+            const int64_t rb_bytes = (int64_t)grid[0] * (grid[1] + 7) * es +
+                                     (int64_t)(grid[0] + grid[1]) * es;
+            if (rb_bytes > lds_max || !fits) {
+                err = "the row-block layout (plane_xmode 5) does not fit in LDS";
+                return VLOC_E_INVALID;
+            }
+            if (p.opt.precision != VLOC_F64 || big_codelet ||
+                (p.opt.plane_threads && p.opt.plane_threads != 768) ||
+                (int64_t)p.nxo * p.sy.L2 > 768) {
+                err = "the row-block layout (plane_xmode 5) needs FP64, 768 plane threads, "
+                      "codelets of at most 16 points and nxo * 8 <= 768";
+                return VLOC_E_INVALID;
+            }
+            p.plane_full = 3;
+            p.plane_xq = 0;
+            p.plane_xw = 0;
+            p.plane_rb = 0;
+            p.plane_rows = 0;
+            p.plane_lds = (int32_t)std::max(full_bytes, rb_bytes);
+            p.plane_threads = 768;
+        } else if (fits && (p.opt.plane_xmode >= 3 || p.opt.plane_xmode == 0)) {
             p.plane_full = p.opt.plane_xmode == 4 ? 2 : 1;
             p.plane_xq = 0;
             p.plane_xw = 0;

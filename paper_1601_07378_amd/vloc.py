@@ -25,7 +25,7 @@ VLOC_E_NOMEM = -6
 VLOC_E_DEVICE = -7
 VLOC_F64 = 0
 VLOC_F32 = 1
-DEALS = {"greedy": 0, "snake": 1, "contiguous": 2}
+DEALS = {"greedy": 0, "snake": 1, "contiguous": 2, "unsorted": 3}
 
 # Every function the header declares; tests check each is exported.
 EXPORTS = [

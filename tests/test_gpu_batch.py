@@ -80,10 +80,13 @@ def test_c4_small_bands_vs_oracle(precision):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_batch_equals_member_plans_bitwise(precision):
-    nbands = (7, 12, 5, 9)
+    # chunk 0: every k-point shares launches; 20: k-points of >= 10 bands
+    # (12, 30) run in launches of their own, the others (7, 5) share one;
+    # 10 and 1: every k-point on its own
+    nbands = (7, 12, 5, 30)
     label(test="batch_vs_members", precision=precision)
     res = {}
-    for chunk in (0, 10, 1):
+    for chunk in (0, 20, 10, 1):
         b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision=precision, band_chunk=chunk)
         cs, V = inputs(b, nbands, C4["ngauss"], C4["kpts"])
         dc, dV = to_dev(cs, V, precision)
@@ -93,7 +96,7 @@ def test_batch_equals_member_plans_bitwise(precision):
         for o, s in zip(outs, solo):
             assert torch.equal(o, s), chunk
         res[chunk] = [o.cpu() for o in outs]
-    for chunk in (10, 1):
+    for chunk in (20, 10, 1):
         for a, c in zip(res[0], res[chunk]):
             assert torch.equal(a, c), chunk
 
@@ -148,8 +151,8 @@ def test_graph_replays_match_eager():
 
 
 def test_c4_full_f32_sampled_vs_oracle():
-    """The full uneven workload (64/128/256/512 bands, FP32, one launch per
-    kernel, graph replay); two bands per k-point against the oracle."""
+    """The full uneven workload (64/128/256/512 bands, FP32, graph replay);
+    two bands per k-point against the oracle."""
     label(test="c4_full")
     b = vloc.Batch(C4["grid"], CELL, ECUT, C4["kpts"], precision="f32")
     cs, V = inputs(b, C4["nbands"], C4["ngauss"], C4["kpts"])

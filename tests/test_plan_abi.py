@@ -73,6 +73,9 @@ def test_stick_map_matches_oracle(grid, cell, ecut, k):
     ps = vloc.Plan(grid, cell, ecut, k, deal="snake")
     gs_ref, _ = oracle.greedy_deal(st_ref[:, 3], ng, "snake")
     assert np.array_equal(ps.stick_groups(), gs_ref)
+    pu = vloc.Plan(grid, cell, ecut, k, deal="unsorted")
+    gu_ref, _ = oracle.greedy_deal(st_ref[:, 3], ng, "unsorted")
+    assert np.array_equal(pu.stick_groups(), gu_ref)
 
 
 @pytest.mark.parametrize("cell,ecut,k,grid,nholes", [(*HOLE_A, (16, 30, 15), 1),

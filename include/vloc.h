@@ -229,9 +229,25 @@ vloc_status vloc_weighted_sum(vloc_plan plan, const double *x, const double *w, 
  * from c_n band chunk by band chunk inside the plane kernel and never stored;
  * partial sums are FP64.  rho: double [N3][N2][N1] (accumulated into);
  * w: double[nbands]; scale: one double s, or NULL for 1.  Needs the row-buffer
- * x pass (plane_xmode 0 or 1); VLOC_E_INVALID otherwise. */
+ * or whole-plane x pass (not plane_xmode 2); VLOC_E_INVALID otherwise. */
 vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const double *w,
                          const double *scale, double *rho);
+/* The application and the weighted density of the same bands in one pass:
+ * out[n] = V_loc c[n] as vloc_apply (bitwise the same result), and
+ * rho(j) += (1/N) sum_n w_n |psi_n(j)|^2 as vloc_density, from the real-space
+ * values the application computes anyway (Sec. 2: psi_n on the grid is the
+ * intermediate of the operator), so the density costs no second transform.
+ * rho: double [N3][N2][N1], accumulated into; w: double[nbands].  out and rho
+ * must not overlap each other or the inputs (VLOC_E_ALIAS).  Needs the
+ * row-buffer or whole-plane x pass (not plane_xmode 2); not for real-mode
+ * plans. */
+vloc_status vloc_apply_density(vloc_plan plan, const void *c, int64_t nbands, const void *V,
+                               void *out, const double *w, double *rho);
+/* y[i] = factor * s * x[i] for i < n (doubles, device); scale (one double s)
+ * may be NULL for 1; y may equal x.  Used to apply the upstream gradient to a
+ * density computed earlier. */
+vloc_status vloc_scale_real(vloc_plan plan, const double *x, int64_t n, const double *scale,
+                            double factor, double *y);
 /* y_n = factor * s * w_n * x_n for n < nbands; w (double[nbands]) and scale
  * (one double s) may be NULL for 1; x, y: [nbands][npw] complex of the plan
  * precision; y may equal x. */

@@ -507,7 +507,7 @@ vloc_status run_launches(Engine &E, int mode, const Launch *ls, size_t nl, const
     t.wts = wts;
     hipError_t e;
     int64_t band0 = 0;
-    if (mode == MODE_APPLY && g.full && nl > 0) {
+    if ((mode == MODE_APPLY || mode == MODE_APPLY_DENSITY) && g.full && nl > 0) {
         // the potential in the full-plane kernel's order, once per call (with
         // arrange false, VT already holds it)
         if (arrange && (e = launch_arrange_v<T>(g, V, VT, st)) != hipSuccess)
@@ -549,7 +549,9 @@ vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, cons
     if (s != VLOC_OK) return s;
     std::vector<Launch> ls;
     const void *ins[1] = {mode == MODE_R2G ? nullptr : in};
-    void *outs[1] = {(mode == MODE_APPLY || mode == MODE_R2G) ? out : nullptr};
+    void *outs[1] = {(mode == MODE_APPLY || mode == MODE_R2G || mode == MODE_APPLY_DENSITY)
+                         ? out
+                         : nullptr};
     // equal chunks of at most band_chunk launch bands (no short last chunk)
     const int64_t units = p->hp.gamma ? (nbands + 1) / 2 : nbands;
     const int64_t nch = (units + p->hp.band_chunk - 1) / p->hp.band_chunk;
@@ -839,13 +841,16 @@ vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, cons
     return err == hipSuccess ? VLOC_OK : hip_fail(err, "band scaling launch");
 }
 
-vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const double *w,
-                         const double *scale, double *rho)
+} // extern "C"
+
+namespace {
+
+// Density passes: checks, band subsets per launch, zeroed FP64 partial planes;
+// then the plane kernel in `mode` (DENSITY or APPLY_DENSITY) and the fixed-order
+// reduction of the partial planes into rho.
+vloc_status density_pass(vloc_plan plan, int mode, const void *c, int64_t nbands, const void *V,
+                         void *out, const double *w, const double *scale, double *rho)
 {
-    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
-    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
-    if (nbands == 0) return VLOC_OK;
-    if (!c || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, w or rho");
     if (plan->hp.gamma) return fail(VLOC_E_INVALID, "real-mode plans only apply");
     if (plan->hp.plane_xq) return fail(VLOC_E_INVALID, "density needs the row-buffer x pass");
     Engine &E = plan->eng;
@@ -891,10 +896,57 @@ vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const do
     }
     hipError_t e = launch_fill_f64(E.d_partial, (int64_t)g.nsub * N, 0.0, E.stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
-    s = dispatch(plan, MODE_DENSITY, c, nbands, nullptr, nullptr, w);
+    s = dispatch(plan, mode, c, nbands, V, out, w);
     if (s != VLOC_OK) return s;
     e = launch_density_reduce(g, E.d_partial, g.nsub, scale, rho, E.stream);
     return e == hipSuccess ? VLOC_OK : hip_fail(e, "density reduce launch");
+}
+
+} // namespace
+
+extern "C" {
+
+vloc_status vloc_density(vloc_plan plan, const void *c, int64_t nbands, const double *w,
+                         const double *scale, double *rho)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!c || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, w or rho");
+    return density_pass(plan, MODE_DENSITY, c, nbands, nullptr, nullptr, w, scale, rho);
+}
+
+vloc_status vloc_apply_density(vloc_plan plan, const void *c, int64_t nbands, const void *V,
+                               void *out, const double *w, double *rho)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (nbands < 0) return fail(VLOC_E_INVALID, "nbands < 0");
+    if (nbands == 0) return VLOC_OK;
+    if (!c || !V || !out || !w || !rho) return fail(VLOC_E_INVALID, "NULL c, V, out, w or rho");
+    const HostPlan &h = plan->hp;
+    const size_t es = (size_t)h.elem_bytes();
+    const size_t cbytes = (size_t)nbands * (size_t)h.npw_io() * es;
+    const size_t nvox = (size_t)h.grid[0] * h.grid[1] * h.grid[2];
+    if (overlaps(out, cbytes, c, cbytes) || overlaps(out, cbytes, V, nvox * (es / 2)) ||
+        overlaps(rho, nvox * 8, out, cbytes) || overlaps(rho, nvox * 8, c, cbytes) ||
+        overlaps(rho, nvox * 8, V, nvox * (es / 2)))
+        return fail(VLOC_E_ALIAS, "out or rho overlaps an input, or each other");
+    if (((uintptr_t)c | (uintptr_t)out) % es || (uintptr_t)V % (es / 2) || (uintptr_t)rho % 8)
+        return fail(VLOC_E_INVALID, "misaligned c, V, out or rho");
+    return density_pass(plan, MODE_APPLY_DENSITY, c, nbands, V, out, w, nullptr, rho);
+}
+
+vloc_status vloc_scale_real(vloc_plan plan, const double *x, int64_t n, const double *scale,
+                            double factor, double *y)
+{
+    if (!plan) return fail(VLOC_E_INVALID, "plan is NULL");
+    if (n < 0) return fail(VLOC_E_INVALID, "n < 0");
+    if (n == 0) return VLOC_OK;
+    if (!x || !y) return fail(VLOC_E_INVALID, "NULL x or y");
+    vloc_status s = upload(plan->eng);
+    if (s != VLOC_OK) return s;
+    hipError_t e = launch_scale_real(x, n, scale, factor, y, plan->eng.stream);
+    return e == hipSuccess ? VLOC_OK : hip_fail(e, "real scaling launch");
 }
 
 vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw)

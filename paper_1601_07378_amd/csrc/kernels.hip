@@ -617,7 +617,10 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
     // contiguous eighth of the items in z-major order (the bands of one z
     // share that XCD's L2 copy of the V plane).  Every workgroup reaches the
     // end of its range.
-    constexpr bool DENS = (MODE == MODE_DENSITY);
+    // density scheduling (items = (z, band subset)) and accumulation; the
+    // multiply by the potential
+    constexpr bool DENS = (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY);
+    constexpr bool POT = (MODE == MODE_APPLY || MODE == MODE_APPLY_DENSITY);
     const int nsub = DENS ? g.nsub : 1;
     const int bps = DENS ? (nb + nsub - 1) / nsub : 1;
     const int total = DENS ? g.N3 * nsub : nb * g.N3;
@@ -870,7 +873,7 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                     cx<T> *row = rows + r * RL + (L2x + 1) * k1;
                     T xr[R], xi[R];
                     T vv[R];
-                    if (MODE == MODE_APPLY) {
+                    if (POT) {
                         const T *vrow = Vz + (long long)y * N1 + k1;
 #pragma unroll
                         for (int k2 = 0; k2 < R; ++k2) vv[k2] = vrow[L1x * k2];
@@ -907,7 +910,16 @@ __device__ __forceinline__ void plane_body(const Geometry &g, const DevTables &t
                             acc[L1x * k2] += wb * (a * a + b * b);
                         }
                     } else {
-                        if (MODE == MODE_APPLY) {
+                        if (MODE == MODE_APPLY_DENSITY) {
+                            const double wb = t.wts[band0 + bl];
+                            double *acc = accz + (long long)y * N1 + k1;
+#pragma unroll
+                            for (int k2 = 0; k2 < R; ++k2) {
+                                const double a = (double)xr[k2], b = (double)xi[k2];
+                                acc[L1x * k2] += wb * (a * a + b * b);
+                            }
+                        }
+                        if (POT) {
 #pragma unroll
                             for (int k2 = 0; k2 < R; ++k2) {
                                 xr[k2] *= vv[k2];
@@ -1083,7 +1095,10 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     };
 
     // work items and persistent XCD-aware schedule as in plane_body
-    constexpr bool DENS = (MODE == MODE_DENSITY);
+    // density scheduling (items = (z, band subset)) and accumulation; the
+    // multiply by the potential
+    constexpr bool DENS = (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY);
+    constexpr bool POT = (MODE == MODE_APPLY || MODE == MODE_APPLY_DENSITY);
     const int nsub = DENS ? g.nsub : 1;
     const int bps = DENS ? (nb + nsub - 1) / nsub : 1;
     const int total = DENS ? g.N3 * nsub : nb * g.N3;
@@ -1125,7 +1140,8 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     // straight to S, so the plane needs no scatter and no gather.  A thread's
     // tasks (yhc, yn2) = tid + u nthr and the slots of their positions stay the
     // same for every plane.
-    constexpr bool DYC = YT > 0 && CY1 > 0 && (MODE == MODE_APPLY || MODE == MODE_DENSITY);
+    constexpr bool DYC = YT > 0 && CY1 > 0 &&
+                         (MODE == MODE_APPLY || MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY);
     constexpr int RY = CY1 > 0 ? CY1 : 1;
     constexpr int NU = YT > 0 ? YT : 1;
     const bool dy = DYC && L.nseg == 1 && nxo * L2y <= NU * nthr;
@@ -1325,7 +1341,7 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             cx<T> *row = plane + L2x * k1 * ldy + yp;
             T xr[R], xi[R];
             T vv[R];
-            if (MODE == MODE_APPLY) {
+            if (POT) {
                 // the task's R values of the potential are contiguous
                 const T *vrun = VTz + ((long long)k1 * N2 + yp) * R;
 #pragma unroll
@@ -1363,7 +1379,16 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                     acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
                 }
             } else {
-                if (MODE == MODE_APPLY) {
+                if (MODE == MODE_APPLY_DENSITY) {
+                    const double wb = t.wts[band0 + bl];
+                    double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) {
+                        const double a = (double)xr[k2], b = (double)xi[k2];
+                        acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+                    }
+                }
+                if (POT) {
 #pragma unroll
                     for (int k2 = 0; k2 < R; ++k2) {
                         xr[k2] *= vv[k2];
@@ -1954,7 +1979,8 @@ static hipError_t launch_plane_sized(const Geometry &g, const DevTables &t, cons
     if (threads <= 512) return go(k_plane<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
     // wide workgroups: compiled for FP64 application and density only, with
     // codelets of at most 16 points
-    if constexpr (std::is_same<T, double>::value && (MODE == MODE_APPLY || MODE == MODE_DENSITY))
+    if constexpr (std::is_same<T, double>::value &&
+                  (MODE == MODE_APPLY || MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY))
         if (plane_codelet_max(g) <= 16) return go(k_plane_wide<T, MODE, X1, X2, Y1, Y2, ZX, ZY>);
     return hipErrorInvalidValue;
 }
@@ -1981,7 +2007,7 @@ hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const L
                                   const void *V, void *psi, int64_t band0, int threads, int lds,
                                   hipStream_t st)
 {
-    if constexpr (MODE != MODE_DENSITY) if (g.xq) {
+    if constexpr (MODE != MODE_DENSITY && MODE != MODE_APPLY_DENSITY) if (g.xq) {
 #define VLOC_QUAD_CASE(XQ, Y1, Y2)                                                                 \
         if (g.xq == XQ && g.L1y == Y1 && g.L2y == Y2)                                             \
             return launch_plane_quad<T, MODE, XQ, Y1, Y2>(g, t, L, S, V, psi, band0, threads,     \
@@ -2031,7 +2057,8 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
     // direct y form: one segment, a specialised y split, apply (and FP32
     // density; the FP64 density kernel would spill with it)
     constexpr bool DYK = Y1 > 0 && (MODE == MODE_APPLY ||
-                                    (MODE == MODE_DENSITY && std::is_same<T, float>::value));
+                                    ((MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY) &&
+                                     std::is_same<T, float>::value));
     const bool dyok = DYK && L.nseg == 1;
     auto pick = [&](auto wpr) {
         constexpr bool W = decltype(wpr)::value;
@@ -2039,7 +2066,8 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
         // codelets of at most 16 points; the diagnostic transforms run the same
         // body on 512 threads
         if constexpr (std::is_same<T, double>::value &&
-                      (MODE == MODE_APPLY || MODE == MODE_DENSITY)) {
+                      (MODE == MODE_APPLY || MODE == MODE_DENSITY ||
+                       MODE == MODE_APPLY_DENSITY)) {
             const bool dy1 = !W && dyok && g.nxo * g.L2y <= threads;
             if (threads > 512 && plane_codelet_max(g) > 16) return hipErrorInvalidValue;
             if (threads > 768) {
@@ -2132,7 +2160,8 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
 {
     if (L.nbt <= 0) return hipSuccess;
     if (mode != MODE_APPLY && L.nseg != 1) return hipErrorInvalidValue;
-    if (mode == MODE_DENSITY && g.xq) return hipErrorInvalidValue; // row-buffer x pass only
+    if ((mode == MODE_DENSITY || mode == MODE_APPLY_DENSITY) && g.xq)
+        return hipErrorInvalidValue; // no density in the lane-quad x pass
     auto run = [&](auto m) {
         constexpr int M = decltype(m)::value;
         return g.full ? launch_plane_full_mode<T, M>(g, t, L, S, V, psi, band0, threads,
@@ -2145,6 +2174,7 @@ hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, 
     case MODE_G2R: return run(std::integral_constant<int, MODE_G2R>{});
     case MODE_R2G: return run(std::integral_constant<int, MODE_R2G>{});
     case MODE_DENSITY: return run(std::integral_constant<int, MODE_DENSITY>{});
+    case MODE_APPLY_DENSITY: return run(std::integral_constant<int, MODE_APPLY_DENSITY>{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -2175,7 +2205,10 @@ hipError_t launch_arrange_v(const Geometry &g, const void *V, void *VT, hipStrea
                                        hipStream_t);                                             \
     template hipError_t F<T, MODE_DENSITY>(const Geometry &, const DevTables &, const Launch &,  \
                                            void *, const void *, void *, int64_t, int, int,      \
-                                           hipStream_t);
+                                           hipStream_t);                                         \
+    template hipError_t F<T, MODE_APPLY_DENSITY>(const Geometry &, const DevTables &,             \
+                                                 const Launch &, void *, const void *, void *,   \
+                                                 int64_t, int, int, hipStream_t);
 #if defined(VLOC_PART_STICK)
 #define VLOC_INSTANTIATE_STICK(T)                                                                 \
     template hipError_t launch_stick_fwd<T>(const Geometry &, const DevTables &, const Launch &, \

@@ -5,7 +5,15 @@
 
 namespace vloc {
 
-enum PlaneMode { MODE_APPLY = 0, MODE_G2R = 1, MODE_R2G = 2, MODE_DENSITY = 3 };
+// APPLY_DENSITY: the application and, from the same real-space values, the
+// weighted density of the launch's bands (one pass instead of two).
+enum PlaneMode {
+    MODE_APPLY = 0,
+    MODE_G2R = 1,
+    MODE_R2G = 2,
+    MODE_DENSITY = 3,
+    MODE_APPLY_DENSITY = 4
+};
 
 // Tables and sizes shared by the kernels of one plan (device pointers).
 struct DevTables {
@@ -81,7 +89,7 @@ hipError_t launch_stick_fwd(const Geometry &g, const DevTables &t, const Launch 
                             int threads, hipStream_t st);
 // K2: plane kernel over the planes of every segment.  APPLY: S -> S in place.
 // G2R: S -> psi rows; R2G: psi -> S; DENSITY: weighted |psi|^2 into the
-// partial planes.  The last three take one segment; psi and the weights are
+// partial planes; APPLY_DENSITY: both APPLY and DENSITY.  The last three take one segment; psi and the weights are
 // indexed from band band0 (the launch's first band in the caller's arrays).
 template <typename T>
 hipError_t launch_plane(const Geometry &g, const DevTables &t, const Launch &L, int mode, void *S,
@@ -99,6 +107,9 @@ hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const L
                                   hipStream_t st);
 // Density helpers (reduce.hip): FP64 reductions and band scaling.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
+// y[i] = factor * s * x[i], s = scale[0] (or 1 if scale is NULL); y may equal x.
+hipError_t launch_scale_real(const double *x, int64_t n, const double *scale, double factor,
+                             double *y, hipStream_t st);
 // partial planes in [z][y][x] order, or with full != 0 in the full-plane
 // kernel's [z][x][yp] order
 hipError_t launch_density_reduce(const Geometry &g, const double *partial, int nsub,

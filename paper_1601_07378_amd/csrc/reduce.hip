@@ -30,6 +30,16 @@ __global__ void k_fill_f64(double *x, long long n, double v)
         x[i] = v;
 }
 
+__global__ void k_scale_real(const double *__restrict__ x, long long n,
+                             const double *__restrict__ scale, double factor,
+                             double *__restrict__ y)
+{
+    const double f = factor * (scale ? scale[0] : 1.0);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = f * x[i];
+}
+
 // rho[j] += scale * inv_n * sum_{s < nsub} partial[s][j'], s ascending, where
 // j = (z, y, x) and j' is j itself, or with full != 0 the full-plane kernel's
 // index (z, x, yp), yp = L2y (y mod L1y) + y / L1y.
@@ -130,6 +140,15 @@ hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, st, x, (long long)n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_real(const double *x, int64_t n, const double *scale, double factor,
+                             double *y, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_real, dim3(grid_for(n)), dim3(256), 0, st, x, (long long)n, scale,
+                       factor, y);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ EXPORTS = [
     "vloc_band_dot", "vloc_weighted_sum", "vloc_density", "vloc_scale_bands",
     "vloc_batch_create", "vloc_batch_destroy", "vloc_batch_plan", "vloc_batch_set_stream",
     "vloc_batch_apply", "vloc_batch_use_graph", "vloc_batch_enable_timing",
-    "vloc_batch_read_timing", "vloc_batch_info", "vloc_apply_noalloc",
+    "vloc_batch_read_timing", "vloc_batch_info", "vloc_apply_noalloc", "vloc_apply_density",
+    "vloc_scale_real",
 ]
 
 
@@ -93,6 +94,8 @@ def lib():
         "vloc_weighted_sum": [vp, vp, vp, i64, vp],
         "vloc_density": [vp, vp, i64, vp, vp, vp],
         "vloc_scale_bands": [vp, vp, i64, vp, vp, ctypes.c_double, vp],
+        "vloc_apply_density": [vp, vp, i64, vp, vp, vp, vp],
+        "vloc_scale_real": [vp, vp, i64, vp, ctypes.c_double, vp],
         "vloc_batch_create": [ctypes.POINTER(vp), i32p, dp, ctypes.c_double, ctypes.c_int32, dp,
                               ctypes.POINTER(Options)],
         "vloc_batch_destroy": [vp],
@@ -166,6 +169,8 @@ class Plan:
         n = ctypes.c_int64()
         check(lib().vloc_plan_npw(self._h, ctypes.byref(n)))
         self.npw = int(n.value)
+        # whole-plane layouts of the plane kernel (plane_xmode 3, 4, 5)
+        self.whole_plane = self.layout()["plane_xmode"] >= 3
 
     @classmethod
     def _borrowed(cls, handle, grid, precision, owner):
@@ -332,6 +337,46 @@ class Plan:
                                  ctypes.c_void_p(scale.data_ptr() if scale is not None else 0),
                                  ctypes.c_void_p(rho.data_ptr())))
         return rho
+
+    def apply_density(self, c, V, w, out=None, rho=None, stream=None):
+        """out = V_loc c and rho += (1/N) sum_n w_n |psi_n|^2 in one pass;
+        returns (out, rho)."""
+        import torch
+        ct, rt = self._dtypes()
+        self._check_c(c)
+        if V.dtype != rt or not V.is_cuda or not V.is_contiguous() or \
+                V.numel() != self.grid[0] * self.grid[1] * self.grid[2]:
+            raise ValueError("V must be a contiguous device tensor of N3*N2*N1 values")
+        self._f64(w, c.shape[0], "w")
+        if out is None:
+            out = torch.empty_like(c)
+        self._check_c(out, "out")
+        N1, N2, N3 = self.grid
+        if rho is None:
+            rho = torch.zeros((N3, N2, N1), dtype=torch.float64, device=c.device)
+        self._f64(rho, N1 * N2 * N3, "rho")
+        self.set_stream(stream)
+        check(lib().vloc_apply_density(self._h, ctypes.c_void_p(c.data_ptr()), c.shape[0],
+                                       ctypes.c_void_p(V.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(w.data_ptr()),
+                                       ctypes.c_void_p(rho.data_ptr())))
+        return out, rho
+
+    def scale_real(self, x, scale=None, factor=1.0, out=None, stream=None):
+        """out = factor * scale * x for a float64 device tensor x."""
+        import torch
+        self._f64(x, x.numel(), "x")
+        if scale is not None:
+            self._f64(scale, 1, "scale")
+        if out is None:
+            out = torch.empty_like(x)
+        self._f64(out, x.numel(), "out")
+        self.set_stream(stream)
+        check(lib().vloc_scale_real(self._h, ctypes.c_void_p(x.data_ptr()), x.numel(),
+                                    ctypes.c_void_p(scale.data_ptr() if scale is not None else 0),
+                                    float(factor), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def scale_bands(self, x, w=None, scale=None, factor=1.0, out=None, stream=None):
         """out_n = factor * scale * w_n * x_n."""

@@ -105,6 +105,44 @@ def test_density_is_deterministic_and_chunk_invariant():
     assert relerr((rho - 1).cpu().numpy(), 2.5 * r1.cpu().numpy()) < 1e-14
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,grid,cell,ecut,k,nb", GRAD_CASES)
+def test_apply_density_one_pass(precision, name, grid, cell, ecut, k, nb):
+    """vloc_apply_density gives vloc_apply's output bit for bit and the density
+    of vloc_density (same per-point band order), both against the oracle."""
+    label(test="apply_density", name=name, precision=precision)
+    hkl = oracle.sphere_py(cell, ecut, k)
+    c = synth.coefficients(hkl, nb, k)
+    V = synth.potential(grid, 4)
+    w = synth.band_weights(nb)
+    if precision == "f32":
+        c = c.astype(np.complex64).astype(np.complex128)
+        V = V.astype(np.float32).astype(np.float64)
+    ct, rt = (torch.complex128, torch.float64) if precision == "f64" else \
+        (torch.complex64, torch.float32)
+    plan = vloc.Plan(grid, cell, ecut, k, precision=precision)
+    tc = torch.from_numpy(c).to("cuda", ct)
+    tV = torch.from_numpy(V).to("cuda", rt)
+    tw = torch.from_numpy(w).cuda()
+    out, rho = plan.apply_density(tc, tV, tw)
+    ref_out = plan.apply(tc, tV)
+    ref_rho = plan.density(tc, tw)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_out)
+    assert relerr(rho.cpu().numpy(), ref_rho.cpu().numpy()) <= 1e-15
+    _, _, rho_or, _ = oracle_refs(grid, cell, ecut, k, c, V, w)
+    tol = 1e-12 if precision == "f64" else 3e-6
+    assert relerr(rho.cpu().numpy().ravel(), rho_or) <= tol
+    # accumulates into rho (rho + rho = 2 rho exactly); the scaling call
+    rho2 = rho.clone()
+    plan.apply_density(tc, tV, tw, rho=rho2)
+    s = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+    scaled = plan.scale_real(rho2, s, factor=4.0)
+    torch.cuda.synchronize()
+    assert torch.equal(rho2, 2.0 * rho)
+    assert torch.equal(scaled, 4.0 * rho)
+
+
 def _energy(plan, c, V, w):
     with torch.no_grad():
         return ag.local_energy(plan, c, V, w).item()

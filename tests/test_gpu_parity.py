@@ -281,3 +281,33 @@ def test_direct_y_form_equals_scatter_form(precision, direct, scatter):
     rd, rs = pd.density(tc, w), ps.density(tc, w)
     torch.cuda.synchronize()
     assert torch.equal(rd, rs)
+
+
+# ------------------------------------------- row-block layout of the plane kernel
+
+@pytest.mark.parametrize("R,k", [(24.0, (0, 0, 0)), (47.0, (0, 0, 0)), (24.0, (0.25, 0.25, 0.0))])
+def test_rowblock_layout_vs_oracle(R, k):
+    """plane_xmode 5 (FP64, 96^3): each wavefront runs one block of eight rows
+    from y stage B to y stage B'; the 47-radius sphere fills 95 of 96 x-planes
+    (760 y tasks on 768 threads).  The diagnostic transforms and the density
+    of such a plan run the whole-plane kernel with its splits."""
+    grid, cell = (96, 96, 96), synth.cubic_cell()
+    ecut = synth.ecut_for_radius(R)
+    label(test="rowblock", R=R, k=k)
+    hkl, c, V = case(grid, cell, ecut, k, 3)
+    p = vloc.Plan(grid, cell, ecut, k, plane_xmode=5)
+    lay = p.layout()
+    assert lay["plane_xmode"] == 5 and (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"]) == (12, 8, 12, 8)
+    got = run(p, c, V)
+    err = relerr_per_band(got, oracle.apply(grid, cell, ecut, k, c, V))
+    print("rowblock R", R, "k", k, "err", err.max())
+    assert err.max() <= TOL64
+    if R == 24.0 and k == (0, 0, 0):
+        psi = p.g2r(dev(c, torch.complex128))
+        w = synth.band_weights(3)
+        rho = p.density(dev(c, torch.complex128), dev(w, torch.float64))
+        torch.cuda.synchronize()
+        psi_ref = oracle.g2r(grid, cell, ecut, k, c)
+        assert relerr(psi.cpu().numpy(), psi_ref) <= TOL64
+        ref = (w[:, None] * np.abs(psi_ref.reshape(3, -1)) ** 2).sum(0) / np.prod(grid)
+        assert relerr(rho.cpu().numpy().ravel(), ref) <= TOL64

@@ -93,17 +93,39 @@ def timed_region(run, steps, stream):
     return e0.elapsed_time(e1)
 
 
-def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, keep=False):
-    """Throughput of one plan on a named workload; optionally a second pass with
-    per-launch events for the kernel split."""
+SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
+
+
+def schedule(grid, cell, ecut, kpts, nbands, precision):
+    """(knobs, source) of the tuned schedule stored for this workload on this
+    device, or ({}, 'planner default')."""
+    from paper_1601_07378_amd import autotune
+    key = autotune._cache_key(grid, cell, ecut, kpts, nbands, precision)
+    if os.path.exists(SCHEDULES):
+        with open(SCHEDULES) as f:
+            entry = json.load(f).get(key)
+        if entry:
+            return entry["best"], "autotuned (paper_1601_07378_amd/schedules.json)"
+    return {}, "planner default"
+
+
+def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, keep=False,
+            tuned=True):
+    """Throughput of one plan on a named workload (with its tuned schedule when
+    one is stored); optionally a second pass with per-launch events for the
+    kernel split."""
     import torch
 
     import synth
-    from paper_1601_07378_amd import vloc
+    from paper_1601_07378_amd import autotune, vloc
 
     w = synth.WORKLOADS[workload]
     grid, cell, ecut, nb = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"]), w["nbands"]
-    plan = vloc.Plan(grid, cell, ecut, precision=precision, gamma=gamma)
+    knobs, source = ({}, "planner default")
+    if tuned and not gamma:
+        knobs, source = schedule(grid, cell, ecut, [(0.0, 0.0, 0.0)], [nb], precision)
+    opts = autotune.to_options(knobs) if knobs else {}
+    plan = vloc.Plan(grid, cell, ecut, precision=precision, gamma=gamma, **opts)
     hkl = plan.gvectors()
     ct, rt = (torch.complex128, torch.float64) if precision == "f64" else (torch.complex64, torch.float32)
     c = torch.from_numpy(synth.coefficients(hkl, nb)).to("cuda", ct)
@@ -119,7 +141,8 @@ def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, k
         run()
     ms = timed_region(run, steps, stream)
     res = dict(plan=plan, grid=grid, nb=nb, ms_step=ms / steps, bands_per_s=nb * steps / (ms / 1e3),
-               sizes=workload_sizes(plan, grid, nb, precision), layout=plan.layout())
+               sizes=workload_sizes(plan, grid, nb, precision), layout=plan.layout(),
+               schedule=knobs or "planner default", schedule_source=source)
     if kernel_pass:
         plan.enable_timing(True)
         plan.read_timing()
@@ -159,9 +182,6 @@ def balance_report(workload):
     return out
 
 
-SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
-
-
 def measure_batch(steps, warmup):
     """Several k-points with uneven spheres and band counts (72x96x128, R = 18,
     4 k-points, 64/128/256/512 bands): the batch (one launch per kernel per
@@ -176,20 +196,17 @@ def measure_batch(steps, warmup):
     grid, cell, ecut = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"])
     kpts, nbs = w["kpts"], w["nbands"]
     total = sum(nbs)
-    tuned, source = {}, "planner default"
-    key = autotune._cache_key(grid, cell, ecut, kpts, nbs, "f32")
-    if os.path.exists(SCHEDULES):
-        with open(SCHEDULES) as f:
-            entry = json.load(f).get(key)
-        if entry:
-            tuned, source = entry["best"], "autotuned (paper_1601_07378_amd/schedules.json)"
+    sched = {p: schedule(grid, cell, ecut, kpts, nbs, p) for p in ("f32", "f64")}
     res = {}
     stream = torch.cuda.current_stream()
-    legs = (("f32", autotune.to_options(tuned) if tuned else {}, True, "f32_batch_graph"),
-            ("f32", {}, False, "f32_plain"),
-            ("f64", {}, False, "f64_batch"),
-            ("f64", {}, False, "f64_plain"))
-    for prec, opts, graph, name in legs:
+    # every leg uses the tuned schedule of its precision (the plain plans take
+    # the same knobs but the batch's band chunk); batches replay HIP graphs
+    legs = (("f32", True, "f32_batch_graph"), ("f32", False, "f32_plain"),
+            ("f64", True, "f64_batch_graph"), ("f64", False, "f64_plain"))
+    for prec, is_batch, name in legs:
+        knobs = sched[prec][0]
+        opts = autotune.to_options(knobs) if knobs else {}
+        plain_opts = {k: v for k, v in opts.items() if k != "band_chunk"}
         ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
             (torch.complex64, torch.float32)
         b = vloc.Batch(grid, cell, ecut, kpts, precision=prec, **opts)
@@ -197,8 +214,8 @@ def measure_batch(steps, warmup):
               for i, (p, nb, k) in enumerate(zip(b.plans, nbs, kpts))]
         outs = [torch.empty_like(c) for c in cs]
         V = torch.from_numpy(synth.potential(grid, w["ngauss"])).to("cuda", rt)
-        if name.endswith("plain"):
-            plans = [vloc.Plan(grid, cell, ecut, k, precision=prec) for k in kpts]
+        if not is_batch:
+            plans = [vloc.Plan(grid, cell, ecut, k, precision=prec, **plain_opts) for k in kpts]
             for p in plans:
                 p.set_stream(stream)
 
@@ -207,8 +224,7 @@ def measure_batch(steps, warmup):
                     p.apply(c, V, out=o, stream=stream)
         else:
             b.set_stream(stream)
-            if graph:
-                b.use_graph(True)
+            b.use_graph(True)
 
             def run():
                 b.apply(cs, V, outs=outs, stream=stream)
@@ -220,15 +236,15 @@ def measure_batch(steps, warmup):
         torch.cuda.empty_cache()
     res["speedup_f32_batch_vs_f32_plain"] = round(res["f32_batch_graph"]["value"] /
                                                   res["f32_plain"]["value"], 3)
-    res["speedup_f64_batch_vs_f64_plain"] = round(res["f64_batch"]["value"] /
+    res["speedup_f64_batch_vs_f64_plain"] = round(res["f64_batch_graph"]["value"] /
                                                   res["f64_plain"]["value"], 3)
     res["speedup_f32_batch_vs_f64_plain"] = round(res["f32_batch_graph"]["value"] /
                                                   res["f64_plain"]["value"], 3)
     res["unit"] = "bands/s"
     res["workload"] = ("72x96x128 grid, |g+k| <= 18, k = (0,0,0), (1/4,0,0), (1/4,1/4,0), "
                        "(1/4,1/4,1/4) with 64/128/256/512 bands (960 per apply)")
-    res["schedule_f32_batch"] = tuned or "planner default"
-    res["schedule_source"] = source
+    res["schedule"] = {p: sched[p][0] or "planner default" for p in sched}
+    res["schedule_source"] = {p: sched[p][1] for p in sched}
     return res
 
 
@@ -291,6 +307,10 @@ def cpu_baseline(nbands_sample: int, threads: int):
     return dict(value=nbands_sample / dt, unit="bands/s", cores=threads, kind="oracle",
                 sample=f"{nbands_sample} of the 256 bands of the 96^3/R=24 workload, "
                        f"FP64, full-cube unpruned FFTs, OpenMP over bands; {dt:.1f} s")
+
+
+def r_default_needed(result) -> bool:
+    return result.get("schedule") != "planner default"
 
 
 def path_figures(r, precision):
@@ -390,6 +410,8 @@ def main():
                                "the same steps",
                      "measured_limiter": "LDS traffic and VALU issue (SQ counters in profiles/)"},
         "kernel_ms_per_step": split,
+        "schedule": r["schedule"],
+        "schedule_source": r["schedule_source"],
     }
     e64 = r["plan"].band_dot(r["c"], r["out"])
     out64 = r["out"]
@@ -404,11 +426,18 @@ def main():
         log("# copy calibration: 268435456 B read + 268435456 B written")
         del src, dst
 
+    # the planner's default schedule on the same workload, for comparison
+    if r_default_needed(result):
+        rd = measure("c2_96", "f64", steps, warmup, kernel_pass=False, tuned=False)
+        result["default_schedule"] = {"value": round(rd["bands_per_s"], 1),
+                                      "ms_per_step": round(rd["ms_step"], 4)}
+        del rd
     # ---- the metric's FP32 column, timed the same way
     r32 = measure("c2_96", "f32", steps, warmup, keep=True)
     f32 = path_figures(r32, "f32")
     s32, a32, b32, lb32, k2s32 = kernel_figures(r32, steps)
     f32["speedup_vs_f64"] = round(r32["bands_per_s"] / head["value"], 3)
+    f32["schedule"] = r32["schedule"]
     f32["kernel_ms_per_step"] = s32
     f32["k2_roofline"] = {"achieved_GBps": round(a32 / 1e9, 1), "frac": round(a32 / HBM_PEAK, 4),
                           "avg_launch_ms": round(k2s32 * 1e3, 4),
@@ -463,8 +492,8 @@ def main():
         rb = measure_batch(steps, warmup)
         result["batched_kpoints"] = rb
         log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} vs f32 plain "
-            f"{rb['f32_plain']['value']:,.0f}; f64 batch {rb['f64_batch']['value']:,.0f} vs f64 "
-            f"plain {rb['f64_plain']['value']:,.0f} bands/s ({rb['schedule_source']})")
+            f"{rb['f32_plain']['value']:,.0f}; f64 graph {rb['f64_batch_graph']['value']:,.0f} vs "
+            f"f64 plain {rb['f64_plain']['value']:,.0f} bands/s ({rb['schedule_source']})")
         rg = measure_grad(max(2, steps // 4), 1)
         result["differentiable_energy"] = rg
         log(f"# energy + gradients 128^3 x 512: f32 {rg['f32']['value']:,.0f} bands/s, "

@@ -24,6 +24,12 @@ import numpy as np
 from . import vloc
 
 CODELETS = (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32)
+# Codelets of the plane kernels of more than 512 threads; the library compiles
+# the whole-plane application kernel for every split of N1 and N2 into two of
+# these for the plane sizes of TUNED_PLANES (with their zero masks), so the
+# splits the tuner tries there run compiled code, not the run-time-sized kernel.
+SMALL_CODELETS = (2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16)
+TUNED_PLANES = ((96, 96), (72, 96), (128, 128))
 
 
 def axis_splits(L: int) -> List[int]:
@@ -35,6 +41,20 @@ def axis_splits(L: int) -> List[int]:
     return out
 
 
+def plane_splits(L: int) -> List[int]:
+    """First factors L1 of the splits L = L1 * L2 into two codelets of at most
+    16 points (those of the compiled tuner kernels)."""
+    return [a for a in SMALL_CODELETS if L % a == 0 and (L // a) in SMALL_CODELETS]
+
+
+def compiled_split(grid, sx: int, sy: int) -> bool:
+    """True when the x and y splits of this plane size have compiled kernels
+    (0 = the planner's split, which always has)."""
+    if (sx == 0 and sy == 0) or tuple(grid[:2]) not in TUNED_PLANES:
+        return sx == 0 and sy == 0
+    return (sx == 0 or sx in plane_splits(grid[0])) and (sy == 0 or sy in plane_splits(grid[1]))
+
+
 def knob_space(grid, precision: str, batch: bool, total_bands: int) -> Dict[str, list]:
     """Candidate values per knob (0 = the planner's automatic choice)."""
     chunks = [0]
@@ -42,17 +62,22 @@ def knob_space(grid, precision: str, batch: bool, total_bands: int) -> Dict[str,
         if c < total_bands:
             chunks.append(c)
     space = {
-        "split_x": [0] + axis_splits(grid[0]),
-        "split_y": [0] + axis_splits(grid[1]),
+        "split_x": [0] + plane_splits(grid[0]),
+        "split_y": [0] + plane_splits(grid[1]),
         "split_z": [0] + axis_splits(grid[2]),
         "sticks_per_group": [0, 8, 16, 24, 32, 48],
         "plane_threads": [0, 256, 384, 512] + ([768, 1024] if precision == "f64" else []),
         "plane_xwaves": [0, 2, 4],
-        "plane_xmode": [0, 1, 2, 3, 4],
+        "plane_xmode": [0, 1, 2, 3, 4] + ([5] if precision == "f64" else []),
         "deal": ["greedy", "contiguous"],
         "band_chunk": chunks,
     }
     return space
+
+
+def thread_choices(precision: str) -> List[int]:
+    """Plane workgroup sizes of the compiled tuner kernels."""
+    return [1024, 768] if precision == "f64" else [512]
 
 
 def to_options(cfg: dict) -> dict:
@@ -166,6 +191,24 @@ class Tuner:
                         self.log(f"# best now {best} {best_t:.4f} ms")
             if not improved:
                 break
+        # coupled step: every compiled (x split, y split, plane threads) triple
+        # from the incumbent, since one split can favour another thread count
+        if "plane_threads" in space:
+            for sx in [0] + plane_splits(self.grid[0]):
+                for sy in [0] + plane_splits(self.grid[1]):
+                    if not compiled_split(self.grid, sx, sy):
+                        continue
+                    for th in thread_choices(self.precision):
+                        cand = dict(best, split_x=sx, split_y=sy, plane_threads=th,
+                                    plane_xmode=0)
+                        if cand == best:
+                            continue
+                        t = self.measure(cand)
+                        self.trials.append(dict(cfg=cand, ms=t, coupled=True))
+                        self.log(f"#   coupled split_x={sx} split_y={sy} threads={th}: {t:.4f} ms")
+                        if t < best_t * (1.0 - self.margin):
+                            best, best_t = cand, t
+                            self.log(f"# best now {best} {best_t:.4f} ms")
         # the incumbent's final time, measured again beside the planner's default
         self.best, self.best_ms = best, self.measure(best)
         self.default_ms = self.measure({k: v[0] for k, v in space.items()})
@@ -186,7 +229,14 @@ def tune_cached(cache_path: Optional[str], grid, cell, ecut, kpts, nbands, preci
     t0 = time.perf_counter()
     best = t.tune()
     entry = dict(best=best, best_ms=t.best_ms, default_ms=t.default_ms,
-                 trials=len(t.trials), seconds=time.perf_counter() - t0)
+                 trials=len(t.trials), seconds=time.perf_counter() - t0,
+                 workload=dict(grid=list(map(int, grid)), ecut=float(ecut),
+                               kpts=np.asarray(kpts, float).round(6).tolist(),
+                               nbands=list(map(int, nbands)), precision=precision),
+                 log=[dict(cfg=tr["cfg"], ms=round(tr["ms"], 4),
+                           compiled=compiled_split(grid, tr["cfg"].get("split_x", 0),
+                                                   tr["cfg"].get("split_y", 0)))
+                      for tr in t.trials])
     if cache_path:
         cache[key] = entry
         tmp = cache_path + ".tmp"

@@ -24,6 +24,11 @@ UNITS = [
                                                  f"-DVLOC_PART_{part.upper()}"])
     for prec in ("f64", "f32") for part in ("full_apply", "full_aux", "rows", "stick")
 ] + [
+    ("kernels.hip", f"kernels_{prec}_tune{gi}.o",
+     [f"-DVLOC_ONLY_{prec.upper()}", "-DVLOC_PART_TUNE", f"-DVLOC_TUNE_T={t}",
+      f"-DVLOC_TUNE_G={gi}"])
+    for prec, t in (("f64", "double"), ("f32", "float")) for gi in range(3)
+] + [
     ("reduce.hip", "reduce.o", []),
     ("plan.cpp", "plan.o", []),
     ("api.cpp", "api.o", []),

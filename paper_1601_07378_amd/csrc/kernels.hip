@@ -1871,14 +1871,17 @@ void k_plane_quad(Geometry g, DevTables t, Launch L, cx<T> *__restrict__ S,
 // arrangement and the plane-kernel dispatch), VLOC_PART_FULL_APPLY and
 // VLOC_PART_FULL_AUX (whole-plane kernels of the application, and of the
 // diagnostic transforms and the density) and VLOC_PART_ROWS (row-buffer and
-// lane-quad kernels).  Without a part macro everything is compiled.
+// lane-quad kernels).  Without a part macro everything but the tuner's
+// specialisations is compiled.
 #if !defined(VLOC_PART_STICK) && !defined(VLOC_PART_FULL_APPLY) &&                               \
-    !defined(VLOC_PART_FULL_AUX) && !defined(VLOC_PART_ROWS)
+    !defined(VLOC_PART_FULL_AUX) && !defined(VLOC_PART_ROWS) && !defined(VLOC_PART_TUNE)
 #define VLOC_PART_STICK
 #define VLOC_PART_FULL_APPLY
 #define VLOC_PART_FULL_AUX
 #define VLOC_PART_ROWS
 #endif
+// VLOC_PART_TUNE (the tuner's specialisations) is compiled once per precision
+// with VLOC_TUNE_T naming it.
 #if defined(VLOC_PART_FULL_APPLY) || defined(VLOC_PART_FULL_AUX)
 #define VLOC_PART_FULL
 #endif
@@ -2147,10 +2150,157 @@ hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const L
     VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
     VLOC_FULL_CASE(4, 6, 4, 6, 0x4, 0x9, 0x4)
 #undef VLOC_FULL_CASE
+    if constexpr (MODE == MODE_APPLY) {
+        bool hit = false;
+        hipError_t err = launch_plane_full_tuned<T>(g, t, L, S, V, threads, lds, st, hit);
+        if (hit) return err;
+    }
     return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
                                                            lds, st);
 }
 #endif // VLOC_PART_FULL
+
+#if defined(VLOC_PART_TUNE)
+// Compiled specialisations for the schedule tuner: every split of the x and y
+// lines into two codelets of at most 16 points, for the plane sizes and
+// occupied ranges of the workloads below, so that a split the tuner tries runs
+// compiled code with its zero masks rather than the run-time-sized kernel.
+// The list is generated at compile time from the workloads (no hand-kept
+// table): N1 x N2 with occupied x-planes [hlo, hhi] and rows [klo, khi].
+struct TuneGeom {
+    int N1, N2, hlo, hhi, klo, khi;
+};
+constexpr TuneGeom kTuneGeoms[] = {
+    {96, 96, -24, 24, -24, 24},  // 96^3 grid, |G| <= 24
+    {72, 96, -18, 18, -18, 18},  // 72 x 96 x 128 grid, |g + k| <= 18 (union over k)
+    {128, 128, -32, 32, -32, 32} // 128^3 grid, |G| <= 32
+};
+constexpr int kNumTuneGeoms = (int)(sizeof kTuneGeoms / sizeof kTuneGeoms[0]);
+constexpr int kTuneCodelets[] = {2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16};
+constexpr int kNumTuneCodelets = (int)(sizeof kTuneCodelets / sizeof kTuneCodelets[0]);
+
+constexpr bool tune_codelet(int r)
+{
+    for (int c : kTuneCodelets)
+        if (c == r) return true;
+    return false;
+}
+// i-th first factor L1 of a split L = L1 L2 with both factors codelets (0 if none)
+constexpr int tune_split(int L, int i)
+{
+    for (int c : kTuneCodelets)
+        if (L % c == 0 && tune_codelet(L / c) && i-- == 0) return c;
+    return 0;
+}
+// Zero and full masks of the stage-A input groups {n2 + L2 n1} for occupied
+// positions [lo, hi] taken mod L (the planner's rule).
+constexpr int tune_mask(int L1, int L2, int lo, int hi, bool full)
+{
+    const int L = L1 * L2;
+    int m = 0;
+    for (int n1 = 0; n1 < L1; ++n1) {
+        bool any = false, all = true;
+        for (int n2 = 0; n2 < L2; ++n2) {
+            const int pos = n2 + L2 * n1;
+            const int r = ((pos - lo) % L + L) % L;
+            const bool occ = lo + r <= hi;
+            any = any || occ;
+            all = all && occ;
+        }
+        if (full ? all : !any) m |= 1 << n1;
+    }
+    return m;
+}
+
+// The variants the planner's thread counts use: FP64 1024 and 768 threads,
+// FP32 512, each in the direct y form where the y tasks fit, else the scatter
+// form.
+template <typename T, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY>
+static hipError_t launch_plane_full_lean(const Geometry &g, const DevTables &t, const Launch &L,
+                                         void *S, const void *VT, int threads, int lds,
+                                         hipStream_t st, bool &hit)
+{
+    auto go = [&](auto kern) {
+        hit = true;
+        hipError_t e = allow_lds(kern, (size_t)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g,
+                           t, L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(VT),
+                           (cx<T> *)nullptr, 0LL);
+        return hipGetLastError();
+    };
+    if (g.full != 1) return hipSuccess;
+    const bool one = L.nseg == 1;
+    if constexpr (std::is_same<T, double>::value) {
+        const bool dy = one && g.nxo * Y2 <= threads;
+        if (threads == 1024)
+            return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, false, 1>)
+                      : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, false, 0>);
+        if (threads == 768)
+            return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 768, false, 1>)
+                      : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 768, false, 0>);
+    } else {
+        const bool dy = one && g.nxo * Y2 <= 2 * threads;
+        if (threads == 512)
+            return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 512, false, 2>)
+                      : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 512, false, 0>);
+    }
+    return hipSuccess;
+}
+
+template <typename T, int G, int IX, int IY>
+static hipError_t try_tuned(const Geometry &g, const DevTables &t, const Launch &L, void *S,
+                            const void *VT, int threads, int lds, hipStream_t st, bool &hit)
+{
+    if (g.N1 != kTuneGeoms[G].N1 || g.N2 != kTuneGeoms[G].N2) return hipSuccess;
+    constexpr TuneGeom tg = kTuneGeoms[G];
+    constexpr int X1 = tune_split(tg.N1, IX), Y1 = tune_split(tg.N2, IY);
+    if constexpr (X1 > 0 && Y1 > 0) {
+        constexpr int X2 = tg.N1 / X1, Y2 = tg.N2 / Y1;
+        constexpr int ZX = tune_mask(X1, X2, tg.hlo, tg.hhi, false);
+        constexpr int FX = tune_mask(X1, X2, tg.hlo, tg.hhi, true);
+        constexpr int ZY = tune_mask(Y1, Y2, tg.klo, tg.khi, false);
+        if (g.N1 == tg.N1 && g.N2 == tg.N2 && g.L1x == X1 && g.L1y == Y1 && (g.zx & ZX) == ZX &&
+            (g.fx & FX) == FX && (g.zy & ZY) == ZY) {
+            hipError_t e =
+                launch_plane_full_lean<T, X1, X2, Y1, Y2, ZX, FX, ZY>(g, t, L, S, VT, threads, lds,
+                                                                      st, hit);
+            if (hit) return e;
+        }
+    }
+    if constexpr (IY + 1 < kNumTuneCodelets)
+        return try_tuned<T, G, IX, IY + 1>(g, t, L, S, VT, threads, lds, st, hit);
+    else if constexpr (IX + 1 < kNumTuneCodelets)
+        return try_tuned<T, G, IX + 1, 0>(g, t, L, S, VT, threads, lds, st, hit);
+    return hipSuccess;
+}
+
+// One part per workload geometry (VLOC_TUNE_G), compiled in parallel.
+template <typename T, int G>
+hipError_t launch_plane_full_tuned_g(const Geometry &g, const DevTables &t, const Launch &L,
+                                     void *S, const void *VT, int threads, int lds,
+                                     hipStream_t st, bool &hit)
+{
+    return try_tuned<T, G, 0, 0>(g, t, L, S, VT, threads, lds, st, hit);
+}
+template hipError_t launch_plane_full_tuned_g<VLOC_TUNE_T, VLOC_TUNE_G>(
+    const Geometry &, const DevTables &, const Launch &, void *, const void *, int, int,
+    hipStream_t, bool &);
+#endif // VLOC_PART_TUNE
+
+#if defined(VLOC_PART_FULL_APPLY)
+template <typename T>
+hipError_t launch_plane_full_tuned(const Geometry &g, const DevTables &t, const Launch &L,
+                                   void *S, const void *VT, int threads, int lds, hipStream_t st,
+                                   bool &hit)
+{
+    hit = false;
+    hipError_t e = launch_plane_full_tuned_g<T, 0>(g, t, L, S, VT, threads, lds, st, hit);
+    if (!hit) e = launch_plane_full_tuned_g<T, 1>(g, t, L, S, VT, threads, lds, st, hit);
+    if (!hit) e = launch_plane_full_tuned_g<T, 2>(g, t, L, S, VT, threads, lds, st, hit);
+    return e;
+}
+#endif
 
 #if defined(VLOC_PART_STICK)
 template <typename T>

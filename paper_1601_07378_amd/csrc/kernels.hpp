@@ -105,6 +105,17 @@ template <typename T, int MODE>
 hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const Launch &L, void *S,
                                   const void *V, void *psi, int64_t band0, int threads, int lds,
                                   hipStream_t st);
+// Compiled specialisations of the whole-plane application kernel for the
+// splits the schedule tuner tries; hit = false where none applies.
+template <typename T>
+hipError_t launch_plane_full_tuned(const Geometry &g, const DevTables &t, const Launch &L,
+                                   void *S, const void *VT, int threads, int lds, hipStream_t st,
+                                   bool &hit);
+// ... those of workload geometry G (one compiled part each)
+template <typename T, int G>
+hipError_t launch_plane_full_tuned_g(const Geometry &g, const DevTables &t, const Launch &L,
+                                     void *S, const void *VT, int threads, int lds,
+                                     hipStream_t st, bool &hit);
 // Density helpers (reduce.hip): FP64 reductions and band scaling.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
 // y[i] = factor * s * x[i], s = scale[0] (or 1 if scale is NULL); y may equal x.

@@ -26,6 +26,24 @@ def test_axis_splits():
             assert L % a == 0 and (L // a) in at.CODELETS
 
 
+def test_plane_splits_and_compiled_table():
+    """The tuner's x / y split candidates are the splits into two codelets of at
+    most 16 points; at the plane sizes the library compiles them for, every
+    pair is compiled (the table is generated from the same rule)."""
+    assert at.plane_splits(96) == [6, 8, 12, 16]
+    assert at.plane_splits(72) == [6, 8, 9, 12]
+    assert at.plane_splits(128) == [8, 16]
+    for grid in ((96, 96, 96), (72, 96, 128), (128, 128, 128)):
+        for sx in [0] + at.plane_splits(grid[0]):
+            for sy in [0] + at.plane_splits(grid[1]):
+                assert at.compiled_split(grid, sx, sy)
+    assert not at.compiled_split((80, 80, 80), 10, 8)
+    assert at.compiled_split((80, 80, 80), 0, 0)
+    # at least three split candidates per axis for the tuned workloads
+    for L in (96, 72):
+        assert len(at.plane_splits(L)) >= 3
+
+
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_every_single_knob_candidate_plans(precision):
     """Each one-knob departure from the defaults is accepted by the planner

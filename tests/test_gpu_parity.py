@@ -311,3 +311,30 @@ def test_rowblock_layout_vs_oracle(R, k):
         assert relerr(psi.cpu().numpy(), psi_ref) <= TOL64
         ref = (w[:, None] * np.abs(psi_ref.reshape(3, -1)) ** 2).sum(0) / np.prod(grid)
         assert relerr(rho.cpu().numpy().ravel(), ref) <= TOL64
+
+
+# ------------------------------------------- the tuner's compiled splits
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tuner_split_kernels_vs_oracle(precision):
+    """Every x / y split the schedule tuner tries at 96^3 (compiled with the
+    workload's zero masks) and a few at 72 x 96 x 128, against the oracle."""
+    at = pytest.importorskip("paper_1601_07378_amd.autotune")
+    label(test="tuner_splits", precision=precision)
+    cases = [((96, 96, 96), 288.0, (0, 0, 0), sx, sy) for sx in at.plane_splits(96)
+             for sy in at.plane_splits(96)]
+    cases += [((72, 96, 128), 162.0, (0.25, 0, 0), sx, sy) for sx, sy in ((6, 6), (9, 12), (12, 16))]
+    cell = synth.cubic_cell()
+    for grid, ecut, k, sx, sy in cases:
+        hkl, c, V = case(grid, cell, ecut, k, 2)
+        p = vloc.Plan(grid, cell, ecut, k, precision=precision, split=(sx, sy, 0))
+        got = run(p, c, V)
+        if precision == "f64":
+            ref, tol = oracle.apply(grid, cell, ecut, k, c, V), TOL64
+        else:
+            ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                               V.astype(np.float32).astype(np.float64))
+            tol = TOL32
+        err = relerr_per_band(got, ref)
+        print(grid, sx, sy, precision, "err", err.max(), flush=True)
+        assert err.max() <= tol, (grid, sx, sy)

@@ -182,7 +182,7 @@ def balance_report(workload):
     return out
 
 
-def measure_batch(steps, warmup):
+def measure_batch(steps, warmup, workload="c4_kpts"):
     """Several k-points with uneven spheres and band counts (72x96x128, R = 18,
     4 k-points, 64/128/256/512 bands): the batch (one launch per kernel per
     chunk) against plain per-k plans applied one after another, in FP32 (graph
@@ -192,7 +192,7 @@ def measure_batch(steps, warmup):
     import synth
     from paper_1601_07378_amd import autotune, vloc
 
-    w = synth.BATCH_WORKLOADS["c4_kpts"]
+    w = synth.BATCH_WORKLOADS[workload]
     grid, cell, ecut = w["grid"], synth.cubic_cell(), synth.ecut_for_radius(w["R"])
     kpts, nbs = w["kpts"], w["nbands"]
     total = sum(nbs)
@@ -241,8 +241,9 @@ def measure_batch(steps, warmup):
     res["speedup_f32_batch_vs_f64_plain"] = round(res["f32_batch_graph"]["value"] /
                                                   res["f64_plain"]["value"], 3)
     res["unit"] = "bands/s"
-    res["workload"] = ("72x96x128 grid, |g+k| <= 18, k = (0,0,0), (1/4,0,0), (1/4,1/4,0), "
-                       "(1/4,1/4,1/4) with 64/128/256/512 bands (960 per apply)")
+    res["workload"] = (f"{grid[0]}x{grid[1]}x{grid[2]} grid, |g+k| <= {w['R']:g}, k = "
+                       + ", ".join("(" + ",".join(f"{x:g}" for x in k) + ")" for k in kpts)
+                       + f" with {'/'.join(map(str, nbs))} bands ({total} per apply)")
     res["schedule"] = {p: sched[p][0] or "planner default" for p in sched}
     res["schedule_source"] = {p: sched[p][1] for p in sched}
     return res
@@ -494,6 +495,11 @@ def main():
         log(f"# batch: f32 graph {rb['f32_batch_graph']['value']:,.0f} vs f32 plain "
             f"{rb['f32_plain']['value']:,.0f}; f64 graph {rb['f64_batch_graph']['value']:,.0f} vs "
             f"f64 plain {rb['f64_plain']['value']:,.0f} bands/s ({rb['schedule_source']})")
+        rs = measure_batch(steps, warmup, "small_kpts")
+        result["batched_small_kpoints"] = rs
+        log(f"# small k-points batch: f32 graph {rs['f32_batch_graph']['value']:,.0f} vs plain "
+            f"{rs['f32_plain']['value']:,.0f}; f64 graph {rs['f64_batch_graph']['value']:,.0f} vs "
+            f"plain {rs['f64_plain']['value']:,.0f} bands/s")
         rg = measure_grad(max(2, steps // 4), 1)
         result["differentiable_energy"] = rg
         log(f"# energy + gradients 128^3 x 512: f32 {rg['f32']['value']:,.0f} bands/s, "

@@ -100,7 +100,10 @@ typedef struct {
                                  in place over the workgroup (N1 (N2 + 1) elements
                                  <= 160 KiB); 4 = as 3 with the x rows owned by
                                  wavefronts (no workgroup barrier inside the x
-                                 pass)                                             */
+                                 pass); 5 = the whole plane in row blocks (FP64,
+                                 768 threads, N1 and N2 = 8 L1: one wavefront
+                                 runs y stage B to y stage B' of eight rows; two
+                                 workgroup barriers per plane)                     */
     int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
                                  each axis (x, y, z); 0 = automatic (the most
                                  balanced split); else L1 and L / L1 must both be
@@ -178,10 +181,15 @@ vloc_status vloc_apply_noalloc(vloc_plan plan, const void *c, int64_t nbands, co
  * coefficients of one band in the caller's arrays (the half sphere for a
  * real-mode plan); the stick, balance and group queries always describe the
  * whole sphere. */
+/* Number of plane waves per band: the size of the cutoff sphere of Sec. 2,
+ * eq. 3 (of its half H in the real mode). */
 vloc_status vloc_plan_npw(vloc_plan plan, int64_t *npw);
-/* hkl: npw*3 int32 (h, k, l) in canonical order. */
+/* hkl: npw*3 int32 (h, k, l) in canonical order: the sphere points of eq. 3,
+ * the coefficient index of c and out. */
 vloc_status vloc_plan_gvectors(vloc_plan plan, int32_t *hkl);
-/* Stick table in canonical order: nsticks rows of (h, k, offset, count, lmin),
+/* The columns that meet the sphere (the first pass of the compact 3-D FFT runs
+ * only on them, Sec. 4.3; here z-sticks).
+ * Stick table in canonical order: nsticks rows of (h, k, offset, count, lmin),
  * where the run [offset .. offset+count) of the whole sphere's canonical order
  * holds l = lmin .. lmin+count-1.  table may be NULL to query the count only. */
 vloc_status vloc_plan_sticks(vloc_plan plan, int64_t *nsticks, int32_t *table);
@@ -189,12 +197,15 @@ vloc_status vloc_plan_sticks(vloc_plan plan, int64_t *nsticks, int32_t *table);
  * the paper's Tab. 2, per workgroup instead of per process).  pw_per_group may
  * be NULL to query the count only. */
 vloc_status vloc_plan_balance(vloc_plan plan, int64_t *ngroups, int64_t *pw_per_group);
-/* Group of each stick (canonical stick order), nsticks int32. */
+/* Group of each stick (canonical stick order), nsticks int32: the column
+ * distribution of Sec. 3.2 (greedy: sorted by plane-wave count, dealt in
+ * turn), with stick groups in place of processes. */
 vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
-/* Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
+/* Schedule of the plan's kernels (implementation choices, no paper quantity).
+ * Sizes chosen by the plan: out[0..7] = {L1x, L2x, L1y, L2y, L1z, L2z,
  * sticks_per_group, band_chunk}; out[8..13] = {plane_rows, plane_threads,
  * plane_lds_bytes, nxo, plane_xwaves, plane_xmode} where nxo is the number of
- * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads), 3 or 4
+ * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads), 3, 4 or 5
  * (whole plane). */
 vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14]);
 
@@ -255,9 +266,11 @@ vloc_status vloc_scale_bands(vloc_plan plan, const void *x, int64_t nbands, cons
                              const double *scale, double factor, void *y);
 
 /* ------------------------------------------- diagnostic full-grid transforms */
-/* Same conventions as vloc_apply: psi_r[n] = psi_n on the whole grid. */
+/* The expansion of eq. 2 on the whole grid, through the compact transform of
+ * Sec. 4.3: psi_r[n] = psi_n (same conventions as vloc_apply). */
 vloc_status vloc_g2r(vloc_plan plan, const void *c, int64_t nbands, void *psi_r);
-/* c_out[n](g) = (1/N) sum_j exp(+2 pi i g.j/N) psi_r[n](j) for g in S. */
+/* Its inverse on the sphere (the second transform of the operator, Sec. 2):
+ * c_out[n](g) = (1/N) sum_j exp(+2 pi i g.j/N) psi_r[n](j) for g in S. */
 vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_out);
 
 /* ------------------------------------------------------------- batches */

@@ -81,4 +81,11 @@ BATCH_WORKLOADS = {
                     kpts=((0.0, 0.0, 0.0), (0.25, 0.0, 0.0), (0.25, 0.25, 0.0),
                           (0.25, 0.25, 0.25)),
                     nbands=(64, 128, 256, 512), ngauss=32),
+    # many k-points with few bands each: the case where one launch over all of
+    # them fills the device and separate per-k launches do not
+    "small_kpts": dict(grid=(72, 96, 128), R=18.0,
+                       kpts=((0.0, 0.0, 0.0), (0.25, 0.0, 0.0), (0.25, 0.25, 0.0),
+                             (0.25, 0.25, 0.25), (0.5, 0.0, 0.0), (0.5, 0.5, 0.0),
+                             (0.5, 0.5, 0.5), (0.25, 0.5, 0.0)),
+                       nbands=(2, 4, 6, 8, 2, 4, 6, 8), ngauss=32),
 }

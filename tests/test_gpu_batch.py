@@ -170,3 +170,29 @@ def test_c4_full_f32_sampled_vs_oracle():
         err = relerr_per_band(o[sample].cpu().numpy().astype(np.complex128), ref)
         print("c4 k", k, "f32 err", err.max())
         assert err.max() <= 2e-6
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_many_small_kpoints_vs_oracle(precision):
+    """Eight k-points with 2-8 bands each (the batch leg where one launch over
+    all k-points matters), graph replay, every band against the oracle."""
+    W = synth.BATCH_WORKLOADS["small_kpts"]
+    label(test="small_kpts", precision=precision)
+    ecut = synth.ecut_for_radius(W["R"])
+    b = vloc.Batch(W["grid"], CELL, ecut, W["kpts"], precision=precision)
+    cs, V = inputs(b, W["nbands"], W["ngauss"], W["kpts"])
+    dc, dV = to_dev(cs, V, precision)
+    b.use_graph(True)
+    outs = b.apply(dc, dV)
+    outs = b.apply(dc, dV, outs=outs)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == "f64" else 2e-6
+    for c, o, k in zip(cs, outs, W["kpts"]):
+        ci, Vi = c, V
+        if precision == "f32":
+            ci = c.astype(np.complex64).astype(np.complex128)
+            Vi = V.astype(np.float32).astype(np.float64)
+        ref = oracle.apply(W["grid"], CELL, ecut, k, ci, Vi)
+        err = relerr_per_band(o.cpu().numpy().astype(np.complex128), ref)
+        print(precision, "k", k, "err", err.max())
+        assert err.max() <= tol

@@ -6,7 +6,8 @@ band chunk.  Inputs are synthetic (seeded), resident in HBM before timing.
 Prints one JSON line on stdout; details go to stderr.
 
 Timing: every throughput figure comes from a timed region with no per-launch
-events (HIP events only at its two ends).  The per-kernel split and the
+events (HIP events only at its two ends), after an untimed warm-up of at least
+--warmup steps and at least 0.3 s (the clock settles in that time).  The per-kernel split and the
 roofline of the dominant kernel come from a second timed region of the same
 steps in which the library records HIP events around each of its launches on
 the plan's stream.
@@ -93,6 +94,24 @@ def timed_region(run, steps, stream):
     return e0.elapsed_time(e1)
 
 
+# Untimed warm-up lasts at least `--warmup` steps and at least this long: the
+# device's clock takes some tens of milliseconds of back-to-back work to settle
+# (K2 launches run about 15% slower in the first ~25 ms of a cold start).
+WARM_MIN_S = 0.3
+
+
+def warm(run, warmup):
+    """`warmup` untimed calls of run(), then more until WARM_MIN_S has passed."""
+    import torch
+    t0 = time.perf_counter()
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    while time.perf_counter() - t0 < WARM_MIN_S:
+        run()
+        torch.cuda.synchronize()
+
+
 SCHEDULES = os.path.join(ROOT, "paper_1601_07378_amd", "schedules.json")
 
 
@@ -137,8 +156,7 @@ def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, k
     def run():
         plan.apply(c, V, out=out, stream=stream)
 
-    for _ in range(warmup):
-        run()
+    warm(run, warmup)
     ms = timed_region(run, steps, stream)
     res = dict(plan=plan, grid=grid, nb=nb, ms_step=ms / steps, bands_per_s=nb * steps / (ms / 1e3),
                sizes=workload_sizes(plan, grid, nb, precision), layout=plan.layout(),
@@ -228,8 +246,7 @@ def measure_batch(steps, warmup, workload="c4_kpts"):
 
             def run():
                 b.apply(cs, V, outs=outs, stream=stream)
-        for _ in range(warmup):
-            run()
+        warm(run, warmup)
         ms = timed_region(run, steps, stream) / steps
         res[name] = {"value": round(total / (ms / 1e3), 1), "ms_per_apply": round(ms, 4)}
         del b, cs, outs, V
@@ -280,8 +297,7 @@ def measure_grad(steps, warmup):
             E.backward()
             return E
 
-        for _ in range(warmup):
-            step()
+        warm(step, warmup)
         ms = timed_region(step, steps, stream) / steps
         res[prec] = {"value": round(nb / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
                      "plane_xmode": plan.layout()["plane_xmode"]}
@@ -369,7 +385,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    log(f"# device: {torch.cuda.get_device_name(0)}")
+    from paper_1601_07378_amd import autotune
+    log(f"# device: {torch.cuda.get_device_name(0)} ({autotune.device_tag()})")
     steps, warmup = args.steps, args.warmup
 
     # ---- headline: 96^3, 256 bands, FP64

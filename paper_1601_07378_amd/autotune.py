@@ -87,13 +87,22 @@ def to_options(cfg: dict) -> dict:
     return opts
 
 
-def _cache_key(grid, cell, ecut, kpts, nbands, precision) -> str:
+def device_tag() -> str:
+    """Architecture and compute-unit count of device 0 (e.g. 'gfx950x256').
+
+    The marketing name is not used: it is not reported the same way in every
+    process (profilers that intercept the runtime change it)."""
     import torch
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.gcnArchName.split(':')[0]}x{p.multi_processor_count}"
+
+
+def _cache_key(grid, cell, ecut, kpts, nbands, precision, device=None) -> str:
     h = hashlib.sha256()
     h.update(json.dumps([list(map(int, grid)), np.asarray(cell, float).round(12).tolist(),
                          float(ecut), np.asarray(kpts, float).round(12).tolist(),
                          list(map(int, nbands)), precision,
-                         torch.cuda.get_device_name(0)]).encode())
+                         device or device_tag()]).encode())
     return h.hexdigest()[:24]
 
 
@@ -233,6 +242,7 @@ def tune_cached(cache_path: Optional[str], grid, cell, ecut, kpts, nbands, preci
                  workload=dict(grid=list(map(int, grid)), ecut=float(ecut),
                                kpts=np.asarray(kpts, float).round(6).tolist(),
                                nbands=list(map(int, nbands)), precision=precision),
+                 device=device_tag(),
                  log=[dict(cfg=tr["cfg"], ms=round(tr["ms"], 4),
                            compiled=compiled_split(grid, tr["cfg"].get("split_x", 0),
                                                    tr["cfg"].get("split_y", 0)))

@@ -85,14 +85,17 @@ typedef struct {
                                  a call is cut into equal chunks of at most this
                                  many; 0 = automatic (stick buffer <= 256 MiB)     */
     int32_t plane_rows;       /* rows per x-pass batch of one wavefront in the plane
-                                 kernel; 0 = automatic                             */
+                                 kernel (plane_xmode 1), rows per part N2 / P
+                                 (plane_xmode 6); 0 = automatic                    */
     int32_t plane_threads;    /* threads per plane workgroup (64..512, multiple of
                                  64; FP64 plans up to 1024 for vloc_apply and
-                                 vloc_density); 0 = automatic                      */
+                                 vloc_density, parted planes up to 1024 for every
+                                 call); 0 = automatic                              */
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
     int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where
-                                 the whole plane fits in LDS, else 1); 1 = the
+                                 the whole plane fits in LDS, else 6 in FP64 and 1
+                                 in FP32); 1 = the
                                  occupied x-planes plus per-wavefront row buffers;
                                  2 = occupied x-planes, one lane quad per x row
                                  (needs N1 in {24, 72, 80, 96} with the matching y
@@ -103,7 +106,14 @@ typedef struct {
                                  pass); 5 = the whole plane in row blocks (FP64,
                                  768 threads, N1 and N2 = 8 L1: one wavefront
                                  runs y stage B to y stage B' of eight rows; two
-                                 workgroup barriers per plane)                     */
+                                 workgroup barriers per plane); 6 = the parted
+                                 plane: the occupied x-planes for the y pass, the
+                                 x pass in P parts of N2 / P rows (P dividing L1y;
+                                 nxo L1y / P <= plane_threads) through one row
+                                 buffer, the other parts in a device scratch of
+                                 nxo N2 values per resident workgroup, allocated
+                                 with the plan's tables; unless split[1] is given
+                                 the longer y codelet comes first                 */
     int32_t split[3];         /* first codelet length L1 of the L = L1 * L2 split of
                                  each axis (x, y, z); 0 = automatic (the most
                                  balanced split); else L1 and L / L1 must both be
@@ -206,7 +216,7 @@ vloc_status vloc_plan_stick_groups(vloc_plan plan, int32_t *group_of_stick);
  * sticks_per_group, band_chunk}; out[8..13] = {plane_rows, plane_threads,
  * plane_lds_bytes, nxo, plane_xwaves, plane_xmode} where nxo is the number of
  * occupied x-planes and plane_xmode is 1 (row buffers), 2 (lane quads), 3, 4 or 5
- * (whole plane). */
+ * (whole plane) or 6 (parted plane; plane_rows is then the rows per part). */
 vloc_status vloc_plan_layout(vloc_plan plan, int32_t out[14]);
 
 /* ------------------------------------------------------- kernel timing */

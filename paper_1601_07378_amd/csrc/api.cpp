@@ -44,6 +44,7 @@ struct Engine {
     double *d_partial = nullptr; // density partial planes
     size_t partial_bytes = 0;
     void *d_VT = nullptr;        // potential in the full-plane kernel's order
+    void *d_parts = nullptr;     // parted plane: nxo x N2 values per resident workgroup
     Geometry geo{};
     // kernel timing: events[4*i .. 4*i+3] bracket K1, K2, K3 of launch i
     bool timing = false;
@@ -116,6 +117,7 @@ void free_device(Engine &E)
     free_ptr(E.d_S);
     free_ptr(E.d_partial);
     free_ptr(E.d_VT);
+    free_ptr(E.d_parts);
     E.partial_bytes = 0;
     E.S_bytes = 0;
     E.uploaded = false;
@@ -192,7 +194,8 @@ vloc_status upload(Engine &E)
             int kp = kk % m->grid[1];
             if (kp < 0) kp += m->grid[1];
             int col = hh - m->hmin;
-            if (m->plane_full) col = ((hh % m->grid[0]) + m->grid[0]) % m->grid[0];
+            if (m->plane_full && m->plane_full != 4)
+                col = ((hh % m->grid[0]) + m->grid[0]) % m->grid[0];
             holes.push_back(col * m->ldy + kp);
         }
         for (int64_t s = 0; s < m->nst(); ++s) {
@@ -201,9 +204,11 @@ vloc_status upload(Engine &E)
             if (lm < 0) lm += m->grid[2];
             int kp = st.k % m->grid[1];
             if (kp < 0) kp += m->grid[1];
-            // plane position: occupied column h - hmin, or in the full plane column h mod N1
+            // plane position: occupied column h - hmin (row buffers, parted plane), or in
+            // the whole plane column h mod N1
             int col = st.h - m->hmin;
-            if (m->plane_full) col = ((st.h % m->grid[0]) + m->grid[0]) % m->grid[0];
+            if (m->plane_full && m->plane_full != 4)
+                col = ((st.h % m->grid[0]) + m->grid[0]) % m->grid[0];
             slot.push_back(make_int4(st.offset, st.count, lm, col * m->ldy + kp));
         }
         for (int g = 0; g < m->ngroups; ++g) {
@@ -308,6 +313,10 @@ vloc_status upload(Engine &E)
         g.zz = h.zz;
         g.fx = h.fx;
         g.full = h.plane_full;
+        g.parts = h.plane_parts;
+        g.parts_elems = std::max(h.nxo * h.ldy, h.grid[0] * (h.plane_parts
+                                                                 ? h.grid[1] / h.plane_parts + 1
+                                                                 : 0));
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E.device) !=
                 hipSuccess ||
@@ -315,6 +324,11 @@ vloc_status upload(Engine &E)
             cus = 256;
         const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, h.plane_lds)));
         g.resident_plane_wgs = cus * per_cu;
+        if (h.plane_full == 4) {
+            // one scratch region per workgroup of the persistent plane grid
+            const size_t pb = (size_t)g.resident_plane_wgs * h.nxo * h.grid[1] * h.elem_bytes();
+            if ((e = hipMalloc(&E.d_parts, pb)) != hipSuccess) goto devfail;
+        }
         g.nsub = 1;
         g.group_cap = cap;
         g.gamma = h.gamma ? 1 : 0;
@@ -373,6 +387,7 @@ DevTables tables(const Engine &E)
     t.gam = E.d_gam;
     t.yslot = E.d_yslot;
     t.holes = E.d_holes;
+    t.parts = E.d_parts;
     return t;
 }
 

@@ -128,7 +128,7 @@ __device__ __forceinline__ void twiddle(T *xr, T *xi, int n2, const cx<T> *__res
 // The same with fewer table reads.  For an 8-point first stage only w^1, w^2
 // and w^4 are read; w^3, w^5, w^6 and w^7 are their products (one or two
 // roundings from the tabulated values): four complex multiplies instead of four
-// reads.  Used where reads are the scarcer resource: the FP64 whole-plane
+// reads; a 16-point stage (FP64) also reads w^8 and forms the rest likewise.  Used where reads are the scarcer resource: the FP64 whole-plane
 // kernel (its LDS traffic is as long as its arithmetic) and, with ANY, the
 // forward stick kernel in both precisions (its twiddle loads were a third of
 // its vector-memory instructions).
@@ -156,6 +156,37 @@ __device__ __forceinline__ void twiddle_pw(T *xr, T *xi, int n2, const cx<T> *__
             xr[k1] = u * wr - v * wi;
             xi[k1] = u * wi + v * wr;
         }
+        return;
+    }
+    if constexpr (R == 16 && (ANY || std::is_same<T, double>::value)) {
+        // w^1, w^2, w^4, w^8 read; w^3 and w^5..w^7 products of them (at most
+        // two roundings), w^9..w^15 = w^(k - 8) w^8 (at most three): 4 reads
+        // and 11 complex multiplies instead of 15 reads, and 8 twiddles live
+        const cx<T> *w_n2 = tw + n2 * R;
+        const cx<T> w1 = w_n2[1], w2 = w_n2[2], w4 = w_n2[4], w8 = w_n2[8];
+        auto mul = [](cx<T> u, cx<T> v) {
+            return mk<T>(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
+        };
+        auto app = [&](int k1, cx<T> w) {
+            T wr = w.x, wi = (S < 0) ? w.y : -w.y;
+            T u = xr[k1], v = xi[k1];
+            xr[k1] = u * wr - v * wi;
+            xi[k1] = u * wi + v * wr;
+        };
+        cx<T> lo[8];
+        lo[0] = mk<T>(T(1), T(0));
+        lo[1] = w1;
+        lo[2] = w2;
+        lo[3] = mul(w1, w2);
+        lo[4] = w4;
+        lo[5] = mul(w1, w4);
+        lo[6] = mul(w2, w4);
+        lo[7] = mul(lo[3], w4);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) app(k, lo[k]);
+        app(8, w8);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) app(8 + k, mul(lo[k], w8));
         return;
     }
     twiddle<R, S, T>(xr, xi, n2, tw);
@@ -1564,6 +1595,465 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
         g, t, L, S, VT, psi, band0);
 }
 
+// ------------------------------------------------------- K2, parted plane
+// For planes that do not fit in LDS whole.  The y passes run on the occupied
+// columns C (nxo x N2, stride ldy, indexed by occupied column hc); the x pass
+// runs in P parts of rpp = N2 / P rows (positions yp of the transposed row
+// order) through one row buffer R (N1 x (rpp + 1), column stride rpp + 1) that
+// shares the LDS with C.  The rows of the parts that are not in R wait in a
+// per-workgroup device scratch G (nxo x N2 values, [hc][yp], small enough to
+// stay mostly in L2):
+//   y stage B      writes part 0 into R and the other parts into G;
+//   x stage A      of part p > 0 reads its occupied inputs from G;
+//   x stage A'     of part p < P - 1 writes its occupied outputs into G, the
+//                  last part keeps them in R;
+//   y stage B'     reads part P - 1 from R and the others from G, then rebuilds C.
+// rpp is a multiple of L2y, so that the rows of one y stage-B line (positions
+// [L2y k1, L2y k1 + L2y)) lie in one part.  Because R overlaps C, the y stage-B
+// lines that write R (part 0) and the y stage-B' lines that read it (part
+// P - 1) hold their values across a barrier, in one round (nxo L1y / P <=
+// threads, checked by the planner).  The y passes use the scatter form (sticks
+// scattered into C and gathered back).  The stage arithmetic is that of the
+// whole-plane kernel.
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
+          int MR>
+__device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTables &t,
+                                                 const Launch &L, cx<T> *__restrict__ S,
+                                                 const T *__restrict__ VT,
+                                                 cx<T> *__restrict__ psi, long long band0)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int L1x = CX1 ? CX1 : g.L1x, L2x = CX2 ? CX2 : g.L2x;
+    const int L1y = CY1 ? CY1 : g.L1y, L2y = CY2 ? CY2 : g.L2y;
+    const int N1 = CX1 ? CX1 * CX2 : g.N1;
+    const int N2 = CY1 ? CY1 * CY2 : g.N2;
+    const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
+    const int P = g.parts, rpp = N2 / P, ldr = rpp + 1;
+    const int nxo = g.nxo, hx = g.hmin_mod;
+    auto div_nxo = [&](int v) {
+        return (int)(((unsigned long long)(unsigned)v * g.nxo_magic) >> 40);
+    };
+    cx<T> *twy = buf + g.parts_elems;
+    cx<T> *twx = twy + N2;
+    int2 *cols = reinterpret_cast<int2 *>(twx + N1);
+    for (int i = tid; i < N2; i += nthr) twy[i] = reinterpret_cast<const cx<T> *>(t.twy)[i];
+    for (int i = tid; i < N1; i += nthr) twx[i] = reinterpret_cast<const cx<T> *>(t.twx)[i];
+    // this workgroup's scratch rows
+    cx<T> *G = reinterpret_cast<cx<T> *>(t.parts) + (long long)blockIdx.x * nxo * N2;
+    const int nb = L.nbt;
+    auto col_of = [&](int hc) {
+        int x = hx + hc;
+        return x >= N1 ? x - N1 : x;
+    };
+    // occupied column of x, or a value >= nxo
+    auto hc_of = [&](int x) {
+        int r = x - hx;
+        return r < 0 ? r + N1 : r;
+    };
+
+    // persistent XCD-aware schedule and density items as in the whole-plane kernel
+    constexpr bool DENS = (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY);
+    constexpr bool POT = (MODE == MODE_APPLY || MODE == MODE_APPLY_DENSITY);
+    const int nsub = DENS ? g.nsub : 1;
+    const int bps = DENS ? (nb + nsub - 1) / nsub : 1;
+    const int total = DENS ? g.N3 * nsub : nb * g.N3;
+    int j0 = blockIdx.x, jstep = gridDim.x, jend = total;
+    if ((gridDim.x & 7) == 0 && (total & 7) == 0) {
+        const int share = total >> 3, xcd = blockIdx.x & 7;
+        j0 = xcd * share + (blockIdx.x >> 3);
+        jstep = gridDim.x >> 3;
+        jend = (xcd + 1) * share;
+    }
+    auto plane_of = [&](int j, int k, int &zz, int &bb) {
+        if (DENS) {
+            zz = j / nsub;
+            bb = (j - zz * nsub) * bps + k;
+        } else {
+            zz = j / nb;
+            bb = j - zz * nb;
+        }
+    };
+    auto advance = [&](int &j, int &k) -> bool {
+        for (;;) {
+            if (DENS && k + 1 < bps)
+                ++k;
+            else {
+                j += jstep;
+                k = 0;
+            }
+            if (j >= jend) return false;
+            int zz, bb;
+            plane_of(j, k, zz, bb);
+            if (bb < nb) return true;
+            k = bps;
+        }
+    };
+    auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
+    // prefetched stick values of slots tid + i nthr and their positions in C
+    int pos[PF];
+    cx<T> pre[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        pos[i] = 0;
+        pre[i] = mk<T>(T(0), T(0));
+    }
+    int spos_seg = -1;
+    auto load_pos = [&](int si) {
+        const Seg sg = seg_at(L, si);
+        const int4 *sl_info = t.slot_info + sg.slot_off;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            pos[i] = sl < sg.nst ? sl_info[sl].w : 0;
+        }
+        for (int i = tid; i < nxo; i += nthr) cols[i] = t.cols[sg.col_off + i];
+        spos_seg = si;
+    };
+    load_pos(0);
+    __syncthreads(); // twiddles and column ranges in LDS
+    auto prefetch = [&](int zz, int bb) {
+        const Seg sg = seg_at(L, seg_of(bb));
+        const cx<T> *Sj = S + sg.s_off + ((long long)(bb - sg.band_lo) * g.N3 + zz) * sg.nst;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int sl = tid + i * nthr;
+            if (sl < sg.nst) pre[i] = Sj[sl];
+        }
+    };
+    int jc = j0, kc = 0;
+    bool have = jc < jend;
+    if (have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        if (bb >= nb) have = advance(jc, kc);
+    }
+    if (MODE != MODE_R2G && have) {
+        int zz, bb;
+        plane_of(jc, kc, zz, bb);
+        prefetch(zz, bb);
+    }
+    constexpr bool XPASS_ONLY_FWD = (MODE == MODE_G2R || MODE == MODE_DENSITY);
+
+    for (; have; have = advance(jc, kc)) {
+    int z, bl;
+    plane_of(jc, kc, z, bl);
+    const int si = seg_of(bl);
+    const Seg sg = seg_at(L, si);
+    const int nst = sg.nst;
+    const int4 *slots = t.slot_info + sg.slot_off;
+    cx<T> *Sz = S + sg.s_off + ((long long)(bl - sg.band_lo) * g.N3 + z) * nst;
+    if (si != spos_seg) load_pos(si);
+    cx<T> *psiz = psi ? psi + (((band0 + bl) * (long long)g.N3 + z) * N2) * N1 : nullptr;
+    const T *VTz = VT ? VT + (long long)z * N1 * N2 : nullptr;
+    double *accz = DENS ? t.partial + ((long long)(bl / bps) * g.N3 + z) * N1 * N2 : nullptr;
+
+    if (MODE != MODE_R2G) {
+        // sticks into C, zeros at the holes of the columns' k spans
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+            if (tid + i * nthr < nst) buf[pos[i]] = pre[i];
+        for (int sl = tid + PF * nthr; sl < nst; sl += nthr) buf[slots[sl].w] = Sz[sl];
+        for (int i = tid; i < sg.nholes; i += nthr)
+            buf[t.holes[sg.hole_off + i]] = mk<T>(T(0), T(0));
+        __syncthreads();
+        // y forward, stage A (lanes along occupied columns)
+        with_size<CY1, MR>(L1y, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < nxo * L2y; task += nthr) {
+                const int n2 = div_nxo(task), hc = task - n2 * nxo;
+                const int2 ci = cols[hc];
+                cx<T> *col = buf + hc * ldy + n2;
+                T xr[R], xi[R];
+#pragma unroll
+                for (int n1 = 0; n1 < R; ++n1) {
+                    cx<T> v = mk<T>(T(0), T(0));
+                    if (!masked<ZY>(n1)) {
+                        int rel = n2 + L2y * n1 - ci.x;
+                        if (rel < 0) rel += N2;
+                        const cx<T> u = col[L2y * n1];
+                        if (rel < ci.y) v = u;
+                    }
+                    xr[n1] = v.x;
+                    xi[n1] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+                twiddle_pw<R, -1, T>(xr, xi, n2, twy);
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) col[L2y * k1] = mk<T>(xr[k1], xi[k1]);
+            }
+        });
+        __syncthreads();
+        // y forward, stage B.  Lines of parts 1.. go to G with no wait; the
+        // lines of part 0 go to R, which overlaps C: they read every input
+        // before a barrier and write after it (one round, nxo L1y / P tasks)
+        with_size<CY2, MR>(L2y, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            const int k1r = L1y / P; // lines k1 < k1r hold the rows of part 0
+            auto line = [&](int hc, int k1, T *xr, T *xi) {
+                const cx<T> *col = buf + hc * ldy + L2y * k1;
+#pragma unroll
+                for (int n2 = 0; n2 < R; ++n2) {
+                    cx<T> v = col[n2];
+                    xr[n2] = v.x;
+                    xi[n2] = v.y;
+                }
+                Dft<R, -1, T>::run(xr, xi);
+            };
+            for (int task = tid; task < nxo * (L1y - k1r); task += nthr) {
+                const int k1 = k1r + div_nxo(task), hc = task - (k1 - k1r) * nxo;
+                T xr[R], xi[R];
+                line(hc, k1, xr, xi);
+                cx<T> *dst = G + (long long)hc * N2 + L2y * k1;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) dst[k2] = mk<T>(xr[k2], xi[k2]);
+            }
+            const int task = tid;
+            const bool act = task < nxo * k1r;
+            const int k1 = div_nxo(task), hc = task - k1 * nxo;
+            T xr[R], xi[R];
+            if (act) line(hc, k1, xr, xi);
+            __syncthreads();
+            if (act) {
+                cx<T> *dst = buf + col_of(hc) * ldr + L2y * k1;
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) dst[k2] = mk<T>(xr[k2], xi[k2]);
+            }
+        });
+        __syncthreads();
+    }
+
+    // x pass, part by part: stage_a forward stage A of row yp (= yb + r) for
+    // n2; stage_b stage B for k1 with the potential, the density or the
+    // real-space values; stage_a2 reverse stage A', occupied outputs only
+    for (int part = 0; part < P; ++part) {
+        const int yb = part * rpp;
+        const bool first = part == 0, last = part == P - 1;
+        if (MODE != MODE_R2G) {
+            with_size<CX1, MR>(L1x, [&](auto RC) {
+                constexpr int R = decltype(RC)::value;
+                for (int task = tid; task < L2x * rpp; task += nthr) {
+                    const int n2 = task / rpp, r = task - n2 * rpp;
+                    cx<T> *row = buf + n2 * ldr + r;
+                    T xr[R], xi[R];
+#pragma unroll
+                    for (int n1 = 0; n1 < R; ++n1) {
+                        cx<T> v = mk<T>(T(0), T(0));
+                        if (!masked<ZX>(n1)) {
+                            const int x = n2 + L2x * n1;
+                            const int hc = hc_of(x);
+                            const bool occ = masked<FX>(n1) || hc < nxo;
+                            if (first) {
+                                const cx<T> u = row[L2x * n1 * ldr];
+                                if (occ) v = u;
+                            } else if (occ) {
+                                v = G[(long long)hc * N2 + yb + r];
+                            }
+                        }
+                        xr[n1] = v.x;
+                        xi[n1] = v.y;
+                    }
+                    Dft<R, -1, T>::run(xr, xi);
+                    twiddle_pw<R, -1, T>(xr, xi, n2, twx);
+#pragma unroll
+                    for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldr] = mk<T>(xr[k1], xi[k1]);
+                }
+            });
+            __syncthreads();
+        }
+        with_size<CX2, MR>(L2x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < L1x * rpp; task += nthr) {
+                const int k1 = task / rpp, r = task - k1 * rpp, yp = yb + r;
+                cx<T> *row = buf + L2x * k1 * ldr + r;
+                T xr[R], xi[R];
+                T vv[R];
+                if (POT) {
+                    const T *vrun = VTz + ((long long)k1 * N2 + yp) * R;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) vv[k2] = vrun[k2];
+                }
+                const int y = (yp % L2y) * L1y + yp / L2y;
+                if (MODE == MODE_R2G) {
+                    const cx<T> *src = psiz + (long long)y * N1 + k1;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) {
+                        cx<T> v = src[L1x * k2];
+                        xr[k2] = v.x;
+                        xi[k2] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int n2 = 0; n2 < R; ++n2) {
+                        cx<T> v = row[n2 * ldr];
+                        xr[n2] = v.x;
+                        xi[n2] = v.y;
+                    }
+                    Dft<R, -1, T>::run(xr, xi);
+                }
+                if (MODE == MODE_G2R) {
+                    cx<T> *dst = psiz + (long long)y * N1 + k1;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
+                } else if (MODE == MODE_DENSITY) {
+                    const double wb = t.wts[band0 + bl];
+                    double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) {
+                        const double a = (double)xr[k2], b = (double)xi[k2];
+                        acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+                    }
+                } else {
+                    if (MODE == MODE_APPLY_DENSITY) {
+                        const double wb = t.wts[band0 + bl];
+                        double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+                        for (int k2 = 0; k2 < R; ++k2) {
+                            const double a = (double)xr[k2], b = (double)xi[k2];
+                            acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+                        }
+                    }
+                    if (POT) {
+#pragma unroll
+                        for (int k2 = 0; k2 < R; ++k2) {
+                            xr[k2] *= vv[k2];
+                            xi[k2] *= vv[k2];
+                        }
+                    }
+                    Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+                    for (int n2 = 0; n2 < R; ++n2) row[n2 * ldr] = mk<T>(xr[n2], xi[n2]);
+                }
+            }
+        });
+        if (last && MODE != MODE_R2G) {
+            // the next plane's stick values, issued after the potential's loads
+            int jn = jc, kn = kc, zz, bb;
+            if (advance(jn, kn)) {
+                plane_of(jn, kn, zz, bb);
+                prefetch(zz, bb);
+            }
+        }
+        __syncthreads();
+        if (XPASS_ONLY_FWD) continue;
+        with_size<CX1, MR>(L1x, [&](auto RC) {
+            constexpr int R = decltype(RC)::value;
+            for (int task = tid; task < L2x * rpp; task += nthr) {
+                const int n2 = task / rpp, r = task - n2 * rpp;
+                cx<T> *row = buf + n2 * ldr + r;
+                T xr[R], xi[R];
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) {
+                    cx<T> v = row[L2x * k1 * ldr];
+                    xr[k1] = v.x;
+                    xi[k1] = v.y;
+                }
+                twiddle_pw<R, +1, T>(xr, xi, n2, twx);
+                Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+                for (int n1 = 0; n1 < R; ++n1) {
+                    if (masked<ZX>(n1)) continue;
+                    const int x = n2 + L2x * n1;
+                    const int hc = hc_of(x);
+                    if (!masked<FX>(n1) && hc >= nxo) continue;
+                    if (last)
+                        row[L2x * n1 * ldr] = mk<T>(xr[n1], xi[n1]);
+                    else
+                        G[(long long)hc * N2 + yb + r] = mk<T>(xr[n1], xi[n1]);
+                }
+            }
+        });
+        __syncthreads();
+    }
+    if (XPASS_ONLY_FWD) continue;
+    // y reverse, stage B', then C rebuilt (it overlaps R): the lines of the
+    // last part read R before a barrier (one round, nxo L1y / P tasks), the
+    // lines of the other parts read G after it
+    with_size<CY2, MR>(L2y, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        const int k1l = L1y - L1y / P; // lines k1 >= k1l hold the rows of the last part
+        auto put = [&](int hc, int k1, T *xr, T *xi) {
+            Dft<R, +1, T>::run(xr, xi);
+            cx<T> *col = buf + hc * ldy + L2y * k1;
+#pragma unroll
+            for (int n2 = 0; n2 < R; ++n2) col[n2] = mk<T>(xr[n2], xi[n2]);
+        };
+        const int task = tid;
+        const bool act = task < nxo * (L1y - k1l);
+        const int k1 = k1l + div_nxo(task), hc = task - (k1 - k1l) * nxo;
+        T xr[R], xi[R];
+        if (act) {
+            const cx<T> *src = buf + col_of(hc) * ldr + (L2y * k1 - (P - 1) * rpp);
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                cx<T> v = src[k2];
+                xr[k2] = v.x;
+                xi[k2] = v.y;
+            }
+        }
+        __syncthreads();
+        if (act) put(hc, k1, xr, xi);
+        for (int tg = tid; tg < nxo * k1l; tg += nthr) {
+            const int k1g = div_nxo(tg), hcg = tg - k1g * nxo;
+            const cx<T> *src = G + (long long)hcg * N2 + L2y * k1g;
+            T yr[R], yi[R];
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                cx<T> v = src[k2];
+                yr[k2] = v.x;
+                yi[k2] = v.y;
+            }
+            put(hcg, k1g, yr, yi);
+        }
+    });
+    __syncthreads();
+    // y reverse, stage A': only stick positions are kept
+    with_size<CY1, MR>(L1y, [&](auto RC) {
+        constexpr int R = decltype(RC)::value;
+        for (int task = tid; task < nxo * L2y; task += nthr) {
+            const int n2 = div_nxo(task), hc = task - n2 * nxo;
+            const int2 ci = cols[hc];
+            cx<T> *col = buf + hc * ldy + n2;
+            T xr[R], xi[R];
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) {
+                cx<T> v = col[L2y * k1];
+                xr[k1] = v.x;
+                xi[k1] = v.y;
+            }
+            twiddle_pw<R, +1, T>(xr, xi, n2, twy);
+            Dft<R, +1, T>::run(xr, xi);
+#pragma unroll
+            for (int n1 = 0; n1 < R; ++n1) {
+                if (masked<ZY>(n1)) continue;
+                int rel = n2 + L2y * n1 - ci.x;
+                if (rel < 0) rel += N2;
+                if (rel < ci.y) col[L2y * n1] = mk<T>(xr[n1], xi[n1]);
+            }
+        }
+    });
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+        if (tid + i * nthr < nst) Sz[tid + i * nthr] = buf[pos[i]];
+    for (int sl = tid + PF * nthr; sl < nst; sl += nthr) Sz[sl] = buf[slots[sl].w];
+    __syncthreads(); // the next plane's scatter overwrites C
+    }
+}
+
+template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
+          int MAXT>
+__global__ __launch_bounds__(MAXT) void k_plane_parts(Geometry g, DevTables t, Launch L,
+                                                      cx<T> *__restrict__ S,
+                                                      const T *__restrict__ VT,
+                                                      cx<T> *__restrict__ psi, long long band0)
+{
+    // prefetched slots per thread cover 2048 slots
+    plane_parts_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT,
+                     (MAXT > 512 ? 16 : 32)>(g, t, L, S, VT, psi, band0);
+}
+
 // ------------------------------------------------------- K2, row blocks
 // Row-block form of the whole-plane kernel (application, launches of one
 // segment, y pass in the direct form).  After y stage A, the L2y-point stage-B
@@ -2127,6 +2617,38 @@ static bool launch_plane_rowblock(const Geometry &g, const DevTables &t, const L
     return false;
 }
 
+// Parted-plane layout: compiled splits for the 128 x 128 planes of the
+// |G| <= 32 sphere (y split 16 x 8, both x splits); any other split runs the
+// same kernel with runtime sizes.
+template <typename T, int MODE>
+static hipError_t launch_plane_parts(const Geometry &g, const DevTables &t, const Launch &L,
+                                     void *S, const void *V, void *psi, int64_t band0,
+                                     int threads, int lds, hipStream_t st)
+{
+    if (!t.parts || g.parts < 1 || threads > 1024 || (threads > 512 && plane_codelet_max(g) > 16))
+        return hipErrorInvalidValue;
+    auto go = [&](auto kern) {
+        hipError_t e = allow_lds(kern, (size_t)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(threads), (size_t)lds, st, g,
+                           t, L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                           reinterpret_cast<cx<T> *>(psi), (long long)band0);
+        return hipGetLastError();
+    };
+#define VLOC_PARTS_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                \
+    if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
+        (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                                   \
+        return threads > 768   ? go(k_plane_parts<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024>)      \
+               : threads > 512 ? go(k_plane_parts<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768>)       \
+                               : go(k_plane_parts<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512>);
+    VLOC_PARTS_CASE(16, 8, 16, 8, 0xFE0, 0xF00F, 0xFE0)
+    VLOC_PARTS_CASE(8, 16, 16, 8, 0x38, 0xC3, 0xFE0)
+#undef VLOC_PARTS_CASE
+    return threads > 768   ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 1024>)
+           : threads > 512 ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 768>)
+                           : go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 512>);
+}
+
 // Whole-plane layout.  Specialised line splits for the common grids; any
 // other split runs the same kernel with runtime sizes.
 template <typename T, int MODE>
@@ -2134,6 +2656,8 @@ hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const L
                                   const void *V, void *psi, int64_t band0, int threads, int lds,
                                   hipStream_t st)
 {
+    if (g.full == 4)
+        return launch_plane_parts<T, MODE>(g, t, L, S, V, psi, band0, threads, lds, st);
     if constexpr (MODE == MODE_APPLY) {
         hipError_t err = hipSuccess;
         if (g.full == 3 && launch_plane_rowblock<T>(g, t, L, S, V, threads, st, err)) return err;

@@ -36,6 +36,9 @@ struct DevTables {
     // stick (zero in the y pass's input); rows [hole_off, hole_off + nholes)
     // of a segment
     const int *holes;
+    // parted plane: per workgroup of the plane grid, nxo x N2 values [hc][yp]
+    // (rows of the parts not in the row buffer)
+    void *parts;
 };
 
 struct Geometry {
@@ -51,7 +54,10 @@ struct Geometry {
     int zx, zy, zz; // zero masks of the first-stage input groups per axis (0 = none)
     int fx;         // x stage-A groups whose every position is occupied
     int full;       // plane kernel holds the whole plane, x pass in place: 1 = spread
-                    // over the workgroup, 2 = rows owned by wavefronts (0 = no)
+                    // over the workgroup, 2 = rows owned by wavefronts, 3 = row blocks;
+                    // 4 = parted plane (0 = row buffers or lane quads)
+    int parts;      // parted plane: x-pass parts of N2 / parts rows
+    int parts_elems; // parted plane: LDS elements of the columns / row buffer region
     int resident_plane_wgs; // plane workgroups resident at once on the device
     int nsub;       // density: band subsets per launch
     int group_cap;  // most sticks in one group (over all segments)

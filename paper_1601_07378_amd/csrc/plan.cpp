@@ -198,11 +198,11 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         (p.opt.plane_threads % 64) != 0 || p.opt.plane_xwaves < 0 ||
         (p.opt.plane_threads > 512 && p.opt.precision != VLOC_F64) ||
         p.opt.plane_xwaves * 64 > (p.opt.plane_threads ? p.opt.plane_threads : 512) ||
-        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 5 || p.opt.gamma < 0 ||
+        p.opt.plane_xmode < 0 || p.opt.plane_xmode > 6 || p.opt.gamma < 0 ||
         p.opt.gamma > 1) {
         err = "option out of range (sticks_per_group 0..64, plane_threads 0 or 64..512 step 64 "
               "(FP64: up to 1024), "
-              "plane_xwaves <= plane_threads / 64, plane_xmode 0..5, gamma 0..1)";
+              "plane_xwaves <= plane_threads / 64, plane_xmode 0..6, gamma 0..1)";
         return VLOC_E_INVALID;
     }
     p.gamma = p.opt.gamma != 0;
@@ -486,7 +486,10 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         if (p.opt.plane_xwaves && xw != p.opt.plane_xwaves) continue;
         const int rpw = (N2 + xw - 1) / xw;
         for (int rb = 1; rb <= rpw; ++rb) {
-            if (p.opt.plane_rows && rb != std::min<int>(p.opt.plane_rows, rpw)) continue;
+            // (plane_rows sizes the parts instead when the parted plane is asked for)
+            if (p.opt.plane_rows && p.opt.plane_xmode != 6 &&
+                rb != std::min<int>(p.opt.plane_rows, rpw))
+                continue;
             const int64_t lds = plane_bytes + (int64_t)xw * rb * p.plane_rl * es;
             if (lds > lds_max) break;
             double total = 0, slowest = 0;
@@ -554,7 +557,7 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
         const int64_t full_bytes = (int64_t)grid[0] * p.ldy * es +
                                    (int64_t)(grid[0] + grid[1]) * es + (int64_t)p.nxo * 8;
         const bool fits = full_bytes <= lds_max;
-        if (p.opt.plane_xmode >= 3 && !fits) {
+        if ((p.opt.plane_xmode == 3 || p.opt.plane_xmode == 4) && !fits) {
             err = "the full plane does not fit in LDS (plane_xmode 3 or 4)";
             return VLOC_E_INVALID;
         }
@@ -589,6 +592,60 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             p.plane_lds = (int32_t)full_bytes;
             p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads
                                                   : (es == 16 && !big_codelet ? 1024 : 512);
+        }
+    }
+    // Parted plane: the occupied columns (nxo x N2) for the y pass and one row
+    // buffer of N2 / P rows (N1 x (N2 / P + 1)) for the x pass, sharing the
+    // LDS; the x pass runs part by part and the rows of the other parts wait
+    // in a per-workgroup device scratch of nxo x N2 values.  P divides L1y, so
+    // that the rows of one y stage-B line lie in one part.  The FP64 default
+    // where the whole plane does not fit (measured faster than the row buffers
+    // at 128^3: 768 threads, the only FP64 width with registers for its 16-point
+    // stages); plane_rows asks for N2 / P rows per part.
+    if (p.opt.plane_xmode == 6 ||
+        (p.opt.plane_xmode == 0 && !p.plane_full && p.opt.precision == VLOC_F64)) {
+        const int nthr = p.opt.plane_threads ? p.opt.plane_threads
+                                             : (big_codelet ? 512 : (es == 16 ? 768 : 1024));
+        // unless asked otherwise, the longer y codelet first: shorter y
+        // stage-B lines to hold across the part barrier
+        Split sx = p.sx, sy = p.sy;
+        if (!p.opt.split[1] && sy.L1 < sy.L2) std::swap(sy.L1, sy.L2);
+        const int64_t cbytes = (int64_t)p.nxo * p.ldy * es;
+        const int64_t extra = (int64_t)(grid[0] + grid[1]) * es + (int64_t)p.nxo * 8;
+        int parts = 0;
+        int64_t lds = 0;
+        for (int P = 2; P <= sy.L1 && !parts; ++P) {
+            if (sy.L1 % P) continue;
+            const int rpp = grid[1] / P;
+            if (p.opt.plane_rows && p.opt.plane_rows != rpp) continue;
+            const int64_t rbytes = (int64_t)grid[0] * (rpp + 1) * es;
+            const int64_t tot = std::max(cbytes, rbytes) + extra;
+            if (tot <= lds_max) {
+                parts = P;
+                lds = tot;
+            }
+        }
+        const bool ok = parts > 0 && (int64_t)p.nxo * (sy.L1 / parts) <= nthr &&
+                        (!big_codelet || nthr <= 512);
+        if (p.opt.plane_xmode == 6 && !ok) {
+            err = "the parted plane (plane_xmode 6) needs a part size N2 / P with P dividing "
+                  "L1y whose row buffer fits in LDS, and nxo * L1y / P <= plane_threads";
+            return VLOC_E_INVALID;
+        }
+        if (ok) {
+            p.sx = sx;
+            p.sy = sy;
+            p.zx = zero_mask(p.sx, p.hmin, p.hmax);
+            p.fx = full_mask(p.sx, p.hmin, p.hmax);
+            p.zy = zero_mask(p.sy, p.kmin, p.kmax);
+            p.plane_full = 4;
+            p.plane_parts = parts;
+            p.plane_xq = 0;
+            p.plane_xw = 0;
+            p.plane_rb = 0;
+            p.plane_rows = grid[1] / parts;
+            p.plane_lds = (int32_t)lds;
+            p.plane_threads = nthr;
         }
     }
     // per occupied x-plane: first k (mod N2) and the span of k from the first

@@ -38,7 +38,10 @@ struct HostPlan {
     int32_t zx = 0, zy = 0, zz = 0; // stage-A input groups that are zero on every line
     int32_t fx = 0;                 // x stage-A groups whose every position is occupied
     int32_t plane_full = 0;         // whole plane in LDS, x pass in place: 1 = spread
-                                    // over the workgroup, 2 = rows per wavefront
+                                    // over the workgroup, 2 = rows per wavefront, 3 = row
+                                    // blocks; 4 = parted plane (see plane_parts)
+    int32_t plane_parts = 0;        // parted plane: x pass in this many parts of N2 / parts
+                                    // rows, the others in a per-workgroup device scratch
 
     // deal of sticks to groups; slots are numbered so that each group's
     // sticks are contiguous

@@ -169,7 +169,8 @@ class Plan:
         n = ctypes.c_int64()
         check(lib().vloc_plan_npw(self._h, ctypes.byref(n)))
         self.npw = int(n.value)
-        # whole-plane layouts of the plane kernel (plane_xmode 3, 4, 5)
+        # layouts whose plane kernel runs the fused application + density
+        # (whole plane: plane_xmode 3, 4, 5; parted plane: 6)
         self.whole_plane = self.layout()["plane_xmode"] >= 3
 
     @classmethod

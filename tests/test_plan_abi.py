@@ -222,6 +222,29 @@ def test_apply_without_device_reports_device_error():
     assert L.vloc_last_error()
 
 
+def test_parted_plane_rules():
+    # forced on a grid whose plane fits whole: parts of N2 / P rows with P
+    # dividing L1y, chosen by plane_rows
+    p = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0, plane_xmode=6)
+    lay = p.layout()
+    assert lay["plane_xmode"] == 6 and (lay["L1y"], lay["L2y"]) == (6, 4)
+    assert lay["plane_rows"] == 12 and lay["plane_threads"] == 768  # fewest parts: P = 2
+    for rows in (12, 8, 4):
+        lay = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0, plane_xmode=6,
+                        plane_rows=rows).layout()
+        assert lay["plane_rows"] == rows and lay["plane_xmode"] == 6
+    with pytest.raises(vloc.VlocError):  # 24 / 5 rows: 5 does not divide L1y
+        vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0, plane_xmode=6, plane_rows=5)
+    # an explicit split is kept
+    lay = vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0, plane_xmode=6,
+                    split=(4, 4, 0)).layout()
+    assert (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"]) == (4, 6, 4, 6)
+    # nxo L1y / P lines of y stage B must fit the workgroup in one round
+    with pytest.raises(vloc.VlocError):
+        vloc.Plan((24, 24, 24), synth.cubic_cell(), 18.0, plane_xmode=6, plane_threads=64,
+                  split=(0, 12, 0), plane_rows=12)
+
+
 def test_layout_defaults():
     p = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0)
     lay = p.layout()
@@ -237,9 +260,20 @@ def test_layout_defaults():
     assert pf.layout()["plane_lds_bytes"] == 96 * 97 * 8 + (96 + 96) * 8 + 49 * 8
     p1 = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=1)
     assert p1.layout()["plane_xmode"] == 1 and p1.layout()["plane_lds_bytes"] <= 160 * 1024
-    # 128^3 FP64: the whole plane (128 x 129 x 16 B) does not fit
+    # 128^3 FP64: the whole plane (128 x 129 x 16 B) does not fit; the parted
+    # plane: 65 columns (stride 129) or a row buffer of 128 x (64 + 1), two
+    # parts, the longer y codelet first (y 16 x 8, x 8 x 16), 768 threads
     p128 = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0)
-    assert p128.layout()["plane_xmode"] == 1
+    lay = p128.layout()
+    assert lay["plane_xmode"] == 6 and lay["plane_rows"] == 64 and lay["plane_threads"] == 768
+    assert (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"]) == (8, 16, 16, 8)
+    assert lay["plane_lds_bytes"] == max(65 * 129, 128 * 65) * 16 + (128 + 128) * 16 + 65 * 8
+    for opts in (dict(plane_xmode=6), dict(plane_xmode=6, plane_threads=768, split=(8, 0, 0)),
+                 dict(plane_xmode=6, plane_rows=32)):
+        lay = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, **opts).layout()
+        assert lay["plane_xmode"] == 6
+    rows = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, plane_xmode=1).layout()
+    assert rows["plane_xmode"] == 1 and (rows["L1x"], rows["L2x"]) == (8, 16)
     with pytest.raises(vloc.VlocError):
         vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, plane_xmode=3)
     assert vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0,

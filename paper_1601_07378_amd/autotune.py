@@ -68,7 +68,7 @@ def knob_space(grid, precision: str, batch: bool, total_bands: int) -> Dict[str,
         "sticks_per_group": [0, 8, 16, 24, 32, 48],
         "plane_threads": [0, 256, 384, 512] + ([768, 1024] if precision == "f64" else []),
         "plane_xwaves": [0, 2, 4],
-        "plane_xmode": [0, 1, 2, 3, 4] + ([5] if precision == "f64" else []),
+        "plane_xmode": [0, 1, 2, 3, 4] + ([5] if precision == "f64" else []) + [6],
         "deal": ["greedy", "contiguous"],
         "band_chunk": chunks,
     }

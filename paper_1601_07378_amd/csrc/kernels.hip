@@ -55,7 +55,9 @@ __device__ __forceinline__ cx<T> mk(T a, T b)
 
 // Calls f with a compile-time codelet size equal to the runtime r.  Sizes
 // above MAXR are not compiled (workgroups of more than 512 threads have too
-// few registers for them); the launchers never run such a kernel with them.
+// few registers for them, and a kernel that holds the paths of larger sizes
+// carries their register pressure into every other size); the launchers never
+// run such a kernel with them.
 template <int MAXR = 32, typename F>
 __device__ __forceinline__ void with_codelet(int r, F &&f)
 {
@@ -80,10 +82,18 @@ __device__ __forceinline__ void with_codelet(int r, F &&f)
     case 6: f(std::integral_constant<int, 6>{}); break;
     case 8: f(std::integral_constant<int, 8>{}); break;
     case 9: f(std::integral_constant<int, 9>{}); break;
-    case 10: f(std::integral_constant<int, 10>{}); break;
-    case 12: f(std::integral_constant<int, 12>{}); break;
-    case 15: f(std::integral_constant<int, 15>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 10:
+        if constexpr (MAXR >= 10) f(std::integral_constant<int, 10>{});
+        break;
+    case 12:
+        if constexpr (MAXR >= 12) f(std::integral_constant<int, 12>{});
+        break;
+    case 15:
+        if constexpr (MAXR >= 15) f(std::integral_constant<int, 15>{});
+        break;
+    case 16:
+        if constexpr (MAXR >= 16) f(std::integral_constant<int, 16>{});
+        break;
     default: break;
     }
 }
@@ -1582,8 +1592,10 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
 // YT > 0: the direct y form with up to YT y tasks per thread (chosen by the
 // launcher when the geometry allows it; a separate instantiation, so that the
 // scatter form does not carry its registers)
+// GMR > 0: the runtime-sized kernel compiled for line codelets of at most
+// GMR points only
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT, bool WPR, int YT>
+          int MAXT, bool WPR, int YT, int GMR = 0>
 __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, Launch L,
                                                      cx<T> *__restrict__ S,
                                                      const T *__restrict__ VT,
@@ -1591,8 +1603,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
 {
     // prefetched slots per thread cover 2048 slots
     plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR, YT,
-                    (MAXT > 512 ? 16 : 32)>(
-        g, t, L, S, VT, psi, band0);
+                    (GMR ? GMR : (MAXT > 512 ? 16 : 32))>(g, t, L, S, VT, psi, band0);
 }
 
 // ------------------------------------------------------- K2, parted plane
@@ -2043,7 +2054,7 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
 }
 
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT>
+          int MAXT, int GMR = 0>
 __global__ __launch_bounds__(MAXT) void k_plane_parts(Geometry g, DevTables t, Launch L,
                                                       cx<T> *__restrict__ S,
                                                       const T *__restrict__ VT,
@@ -2051,7 +2062,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_parts(Geometry g, DevTables t, L
 {
     // prefetched slots per thread cover 2048 slots
     plane_parts_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT,
-                     (MAXT > 512 ? 16 : 32)>(g, t, L, S, VT, psi, band0);
+                     (GMR ? GMR : (MAXT > 512 ? 16 : 32))>(g, t, L, S, VT, psi, band0);
 }
 
 // ------------------------------------------------------- K2, row blocks
@@ -2402,6 +2413,16 @@ static hipError_t allow_lds(K kernel, size_t bytes)
     return std::max(std::max(g.L1x, g.L2x), std::max(g.L1y, g.L2y));
 }
 
+// Class of the runtime-sized plane kernels for this plan: codelets of at most
+// 10 or 12 points, else every size (0).  With the 15- and 16-point paths an
+// FP64 kernel of 1024 threads spills 130 registers; limited to 10 points it
+// spills none.
+[[maybe_unused]] static int plane_codelet_class(const Geometry &g)
+{
+    const int m = plane_codelet_max(g);
+    return m <= 10 ? 10 : (m <= 12 ? 12 : 0);
+}
+
 #if defined(VLOC_PART_STICK)
 // Line splits and zero masks compiled as specialisations of the stick
 // kernels; any other plan runs the same kernels with runtime sizes.  A
@@ -2534,7 +2555,9 @@ hipError_t launch_plane_rows_mode(const Geometry &g, const DevTables &t, const L
 #endif // VLOC_PART_ROWS
 
 #if defined(VLOC_PART_FULL)
-template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY>
+// GMR: class of the runtime-sized kernel (plane_codelet_class; 0 otherwise)
+template <typename T, int MODE, int X1, int X2, int Y1, int Y2, int ZX, int FX, int ZY,
+          int GMR = 0>
 static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const Launch &L,
                                     void *S, const void *VT, void *psi, int64_t band0,
                                     int threads, int lds, hipStream_t st)
@@ -2555,6 +2578,7 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
     const bool dyok = DYK && L.nseg == 1;
     auto pick = [&](auto wpr) {
         constexpr bool W = decltype(wpr)::value;
+        constexpr int G = W ? 0 : GMR;
         // more than 512 threads: compiled for FP64 application and density with
         // codelets of at most 16 points; the diagnostic transforms run the same
         // body on 512 threads
@@ -2566,23 +2590,23 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
             if (threads > 768) {
                 if constexpr (DYK && !W)
                     if (dy1)
-                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1>,
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1, G>,
                                   threads);
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0>, threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0, G>, threads);
             }
             if (threads > 512) {
                 if constexpr (DYK && !W)
                     if (dy1)
-                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 1>,
+                        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 1, G>,
                                   threads);
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 0>, threads);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 768, W, 0, G>, threads);
             }
         }
         const int nt = threads < 512 ? threads : 512;
         if constexpr (DYK && !W && std::is_same<T, float>::value)
             if (dyok && g.nxo * g.L2y <= 2 * nt)
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2>, nt);
-        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0>, nt);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);
+        return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0, G>, nt);
     };
     if (g.full == 2) return pick(std::true_type{});
     return pick(std::false_type{});
@@ -2644,9 +2668,17 @@ static hipError_t launch_plane_parts(const Geometry &g, const DevTables &t, cons
     VLOC_PARTS_CASE(16, 8, 16, 8, 0xFE0, 0xF00F, 0xFE0)
     VLOC_PARTS_CASE(8, 16, 16, 8, 0x38, 0xC3, 0xFE0)
 #undef VLOC_PARTS_CASE
-    return threads > 768   ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 1024>)
-           : threads > 512 ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 768>)
-                           : go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 512>);
+    auto generic = [&](auto cls) {
+        constexpr int C = decltype(cls)::value;
+        return threads > 768   ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 1024, C>)
+               : threads > 512 ? go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 768, C>)
+                               : go(k_plane_parts<T, MODE, 0, 0, 0, 0, 0, 0, 0, 512, C>);
+    };
+    switch (plane_codelet_class(g)) {
+    case 10: return generic(std::integral_constant<int, 10>{});
+    case 12: return generic(std::integral_constant<int, 12>{});
+    default: return generic(std::integral_constant<int, 0>{});
+    }
 }
 
 // Whole-plane layout.  Specialised line splits for the common grids; any
@@ -2679,8 +2711,17 @@ hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const L
         hipError_t err = launch_plane_full_tuned<T>(g, t, L, S, V, threads, lds, st, hit);
         if (hit) return err;
     }
-    return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
-                                                           lds, st);
+    switch (plane_codelet_class(g)) {
+    case 10:
+        return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0, 10>(g, t, L, S, V, psi, band0,
+                                                                   threads, lds, st);
+    case 12:
+        return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0, 12>(g, t, L, S, V, psi, band0,
+                                                                   threads, lds, st);
+    default:
+        return launch_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0>(g, t, L, S, V, psi, band0, threads,
+                                                               lds, st);
+    }
 }
 #endif // VLOC_PART_FULL
 

@@ -338,3 +338,34 @@ def test_tuner_split_kernels_vs_oracle(precision):
         err = relerr_per_band(got, ref)
         print(grid, sx, sy, precision, "err", err.max(), flush=True)
         assert err.max() <= tol, (grid, sx, sy)
+
+
+# --------------------------- runtime-sized kernels, by codelet class
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("grid,ecut,split,cls", [
+    ((20, 24, 18), 12.0, (2, 0, 0), 10),     # x = 2 x 10, y = 4 x 6: the <= 10 class
+    ((24, 24, 20), 18.0, (2, 0, 0), 12),     # x = 2 x 12: the <= 12 class
+    ((32, 30, 24), 18.0, (2, 2, 0), 16),     # x = 2 x 16, y = 2 x 15: every size
+])
+def test_runtime_sized_classes_vs_oracle(precision, grid, ecut, split, cls):
+    """Plans with no compiled specialisation run the runtime-sized plane kernel
+    of the smallest codelet class that covers their largest line codelet (at
+    most 10, 12 or 16 points); each class against the oracle."""
+    cell, k = SKEW, (0.1, -0.2, 0.3)
+    label(test="runtime_sized", grid=grid, split=split, precision=precision)
+    hkl, c, V = case(grid, cell, ecut, k, 3)
+    p = vloc.Plan(grid, cell, ecut, k, precision=precision, split=split)
+    lay = p.layout()
+    biggest = max(lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"])
+    assert {10: 0, 12: 10, 16: 12}[cls] < biggest <= cls
+    got = run(p, c, V)
+    if precision == "f64":
+        ref, tol = oracle.apply(grid, cell, ecut, k, c, V), TOL64
+    else:
+        ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                           V.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    err = relerr_per_band(got, ref)
+    print(grid, split, precision, "class", cls, "err", err.max())
+    assert err.max() <= tol

@@ -106,3 +106,19 @@ def test_tuner_pick_is_correct(require_gpu, tmp_path):
         ref = oracle.apply(grid, cell, ecut, k, c, V)
         err = np.linalg.norm(o.cpu().numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
         assert err.max() <= 1e-12
+
+
+def test_stored_schedule_keys_match_their_workloads():
+    """Every entry of the committed schedule store sits under the key that its
+    recorded workload and device give (so a lookup by workload finds it)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(at.__file__), "schedules.json")
+    with open(path) as f:
+        store = json.load(f)
+    assert store
+    for key, e in store.items():
+        w = e["workload"]
+        assert "device" in e
+        assert at._cache_key(w["grid"], synth.cubic_cell(), w["ecut"], w["kpts"], w["nbands"],
+                             w["precision"], device=e["device"]) == key

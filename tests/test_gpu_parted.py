@@ -3,8 +3,9 @@ the occupied columns for the y pass, the x pass in parts of N2 / P rows
 through one row buffer, the other parts in a per-workgroup device scratch.
 
 Forced on small grids (every part count the planner allows, FP64 and FP32,
-skewed cells and k-shifts, the diagnostic transforms and the density), and the
-default layout of the 128^3 FP64 plans, all against the CPU oracle.  FP64 gate
+skewed cells and k-shifts, the diagnostic transforms, the density, the real
+mode, batches and the allocation-free entry point), and the default layout of
+the 128^3 FP64 plans, all against the CPU oracle.  FP64 gate
 1e-12 per band; FP32 2e-6 against the oracle on FP32-rounded inputs."""
 import numpy as np
 import pytest
@@ -119,7 +120,7 @@ def test_parted_transforms_and_density(precision):
 
 def test_parted_128_default_layout_vs_oracle():
     """The default FP64 layout at 128^3 with the |G| <= 32 sphere (two parts of
-    64 rows, the compiled 16 x 8 splits), over two band chunks."""
+    64 rows, the compiled x 8 x 16 / y 16 x 8 splits), over two band chunks."""
     grid, cell, ecut, k = (128, 128, 128), synth.cubic_cell(), 512.0, (0, 0, 0)
     label(test="parted_128")
     hkl = oracle.sphere_py(cell, ecut, k)
@@ -160,3 +161,29 @@ def test_parted_batch_and_noalloc():
     p.apply_noalloc(cs[1], Vd, out)
     torch.cuda.synchronize()
     assert torch.equal(out, first)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_parted_real_mode_vs_oracle(precision):
+    """The real (Gamma) mode on a parted plan: two real bands per complex
+    transform through the parted plane kernel (odd band count)."""
+    grid, cell, ecut = (24, 24, 24), synth.cubic_cell(), 18.0
+    label(test="parted_gamma", precision=precision)
+    p = vloc.Plan(grid, cell, ecut, precision=precision, gamma=True, plane_xmode=6,
+                  plane_rows=8)
+    assert p.layout()["plane_xmode"] == 6
+    c = synth.coefficients(p.gvectors(), 5)
+    V = synth.potential(grid, 4)
+    ct, rt = types(precision)
+    got = p.apply(dev(c, ct), dev(V, rt))
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.complex128)
+    if precision == "f64":
+        ref, tol = oracle.apply_gamma(grid, cell, ecut, c, V), TOL64
+    else:
+        ref = oracle.apply_gamma(grid, cell, ecut, c.astype(np.complex64).astype(np.complex128),
+                                 V.astype(np.float32).astype(np.float64))
+        tol = TOL32
+    err = relerr_per_band(got, ref)
+    print("parted gamma", precision, "err", err.max())
+    assert err.max() <= tol

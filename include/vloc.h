@@ -288,14 +288,17 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
  * with its own cutoff sphere and band count) applied together (the paper's
  * balancing of uneven units, Sec. 3.2, carried to whole k-points; Sec. 1 on
  * aggregating the transforms of many bands).  A k-point with at least half a
- * band chunk of bands fills the device by itself and runs in launches of its
- * own (its bands cut into equal chunks); the bands of the smaller k-points are
- * concatenated (k-point order) and each chunk of them runs as ONE launch of
- * each kernel, whose workgroups take planes and stick groups of every k-point
- * in it from one work list.  All launches of a call are stream-ordered and can
- * be replayed as one HIP graph (vloc_batch_use_graph).  The members share one plane layout: each covers the union
- * of the k-points' occupied x-planes, so a member's own results equal those
- * of a stand-alone plan of the same k. */
+ * band chunk of bands, or with enough bands that its z-planes fill the resident
+ * plane workgroups four times over, runs in launches of its own (its bands cut
+ * into equal chunks); the bands of the smaller k-points are concatenated
+ * (k-point order) and each chunk of them runs as ONE launch of each kernel,
+ * whose workgroups take planes and stick groups of every k-point in it from one
+ * work list.  All launches of a call are stream-ordered and can be replayed as
+ * one HIP graph (vloc_batch_use_graph).  The members share one plane layout.
+ * With the whole-plane layouts (plane_xmode 3 and 4) each member keeps its own
+ * occupied x-planes (each launch segment carries them); with the others each
+ * member covers the union of the k-points' occupied x-planes.  Either way a
+ * member plan's own results (vloc_batch_plan) equal its part of the batch. */
 typedef struct vloc_batch_s *vloc_batch; /* opaque; owned by the library */
 
 /* nk in [1, 8]; kpts: nk*3 doubles (reduced coordinates, as for a plan).

@@ -53,7 +53,15 @@ struct Engine {
     std::vector<int> rec_modes;
     // orders work across a change of stream (the stick buffer is reused)
     hipEvent_t order_ev = nullptr;
+    // LDS bytes of the plane launches when the members' own sizes differ (a
+    // batch on its members' own occupied ranges); 0 = the first member's
+    int32_t plane_lds = 0;
 };
+
+static int32_t plane_lds(const Engine &E)
+{
+    return E.plane_lds ? E.plane_lds : E.members[0]->plane_lds;
+}
 
 struct vloc_plan_s {
     HostPlan hp;
@@ -64,6 +72,7 @@ struct vloc_plan_s {
 struct vloc_batch_s {
     std::vector<vloc_plan_s *> plans; // members, owned
     Engine eng;
+    int32_t lds = 0;                  // LDS bytes of the batch's plane launches
     int64_t band_chunk = 0;           // bands per launch over all k-points; 0 = all
     // HIP graph of the last call's launches, replayed while the call's
     // pointers and band counts stay the same
@@ -308,10 +317,18 @@ vloc_status upload(Engine &E)
         g.rl = h.plane_rl;
         g.xw = h.plane_xw;
         g.xq = h.plane_xq;
+        // masks that hold for every member (members on their own occupied
+        // ranges differ in them)
         g.zx = h.zx;
         g.zy = h.zy;
         g.zz = h.zz;
         g.fx = h.fx;
+        for (const HostPlan *m : E.members) {
+            g.zx &= m->zx;
+            g.zy &= m->zy;
+            g.zz &= m->zz;
+            g.fx &= m->fx;
+        }
         g.full = h.plane_full;
         g.parts = h.plane_parts;
         g.parts_elems = std::max(h.nxo * h.ldy, h.grid[0] * (h.plane_parts
@@ -322,7 +339,7 @@ vloc_status upload(Engine &E)
                 hipSuccess ||
             cus < 1)
             cus = 256;
-        const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, h.plane_lds)));
+        const int per_cu = std::max(1, std::min(2, (160 * 1024) / std::max(1, plane_lds(E))));
         g.resident_plane_wgs = cus * per_cu;
         if (h.plane_full == 4) {
             // one scratch region per workgroup of the persistent plane grid
@@ -434,6 +451,9 @@ void fill_seg(const Engine &E, int member, const void *in, void *out, int64_t nb
     s.col_off = E.col_off[member];
     s.hole_off = E.hole_off[member];
     s.nholes = E.nholes[member];
+    s.nxo = m.nxo;
+    s.hmin_mod = ((m.hmin % m.grid[0]) + m.grid[0]) % m.grid[0];
+    s.nxo_magic = ((1ull << 40) + (unsigned)m.nxo - 1) / (unsigned)m.nxo;
     s.band_lo = band_lo;
     s.nb = nb;
     s.blk_lo = blk_lo;
@@ -542,7 +562,7 @@ vloc_status run_launches(Engine &E, int mode, const Launch *ls, size_t nl, const
             if (e != hipSuccess) return hip_fail(e, "stick forward launch");
         }
         if (timed) (void)hipEventRecord(ev[1], st);
-        e = launch_plane<T>(g, t, L, mode, S, V, psi, band0, h.plane_threads, h.plane_lds, st);
+        e = launch_plane<T>(g, t, L, mode, S, V, psi, band0, h.plane_threads, plane_lds(E), st);
         if (e != hipSuccess) return hip_fail(e, "plane launch");
         if (timed) (void)hipEventRecord(ev[2], st);
         if (mode != MODE_G2R && mode != MODE_DENSITY) {
@@ -1048,9 +1068,13 @@ vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const do
         // pass 1: each k-point's own sphere and occupied ranges
         Occupied u{};
         for (int i = 0; i < nk && s == VLOC_OK; ++i) {
-            HostPlan h;
-            s = build_host_plan(h, grid, cell, ecut, kpts + 3 * i, opt, err);
+            vloc_plan p = new vloc_plan_s();
+            p->borrowed = true;
+            b->plans.push_back(p);
+            s = build_host_plan(p->hp, grid, cell, ecut, kpts + 3 * i, opt, err);
+            p->eng.members.assign(1, &p->hp);
             if (s != VLOC_OK) break;
+            const HostPlan &h = p->hp;
             if (i == 0) u = Occupied{h.hmin, h.hmax, h.kmin, h.kmax, h.lmin, h.lmax};
             u.hmin = std::min(u.hmin, h.hmin);
             u.hmax = std::max(u.hmax, h.hmax);
@@ -1059,25 +1083,45 @@ vloc_status vloc_batch_create(vloc_batch *batch, const int32_t grid[3], const do
             u.lmin = std::min(u.lmin, h.lmin);
             u.lmax = std::max(u.lmax, h.lmax);
         }
-        // pass 2: every member laid out on the union of the ranges
-        for (int i = 0; i < nk && s == VLOC_OK; ++i) {
-            vloc_plan p = new vloc_plan_s();
-            p->borrowed = true;
-            b->plans.push_back(p);
-            s = build_host_plan(p->hp, grid, cell, ecut, kpts + 3 * i, opt, err, &u);
-            p->eng.members.assign(1, &p->hp);
+        // The whole-plane layouts (x pass spread over the workgroup or rows
+        // owned by wavefronts) keep each member on its own occupied range:
+        // launch segments carry their occupied x-planes, the engine takes the
+        // zero and full masks that hold for every member and the largest LDS
+        // size.  Every other layout sizes LDS or row buffers by the occupied
+        // range, so the members are laid out again on the union of the ranges.
+        bool own = s == VLOC_OK;
+        for (size_t i = 0; own && i < b->plans.size(); ++i) {
+            const HostPlan &h = b->plans[i]->hp, &h0 = b->plans[0]->hp;
+            own = (h.plane_full == 1 || h.plane_full == 2) && h.plane_full == h0.plane_full &&
+                  h.plane_threads == h0.plane_threads && h.sx.L1 == h0.sx.L1 &&
+                  h.sy.L1 == h0.sy.L1 && h.sz.L1 == h0.sz.L1;
+        }
+        if (s == VLOC_OK && !own) {
+            for (int i = 0; i < nk && s == VLOC_OK; ++i) {
+                vloc_plan p = b->plans[i];
+                p->hp = HostPlan();
+                s = build_host_plan(p->hp, grid, cell, ecut, kpts + 3 * i, opt, err, &u);
+                p->eng.members.assign(1, &p->hp);
+            }
         }
         if (s == VLOC_OK) {
             const HostPlan &h0 = b->plans[0]->hp;
+            int32_t lds = 0;
+            for (vloc_plan p : b->plans) lds = std::max(lds, p->hp.plane_lds);
             for (vloc_plan p : b->plans) {
                 const HostPlan &h = p->hp;
-                if (h.nxo != h0.nxo || h.hmin != h0.hmin || h.zx != h0.zx || h.zy != h0.zy ||
-                    h.zz != h0.zz || h.plane_lds != h0.plane_lds || h.plane_xw != h0.plane_xw ||
-                    h.plane_rb != h0.plane_rb || h.plane_xq != h0.plane_xq) {
+                if ((!own && (h.nxo != h0.nxo || h.hmin != h0.hmin || h.zx != h0.zx ||
+                              h.zy != h0.zy || h.zz != h0.zz || h.plane_lds != h0.plane_lds)) ||
+                    h.plane_full != h0.plane_full || h.plane_xw != h0.plane_xw ||
+                    h.plane_rb != h0.plane_rb || h.plane_xq != h0.plane_xq ||
+                    h.plane_threads != h0.plane_threads) {
                     s = VLOC_E_INVALID;
                     err = "internal: batch members disagree on the plane layout";
                 }
             }
+            // one LDS size for every launch (the member plans' own calls keep theirs)
+            b->lds = lds;
+            b->eng.plane_lds = lds;
             for (vloc_plan p : b->plans) b->eng.members.push_back(&p->hp);
             b->band_chunk = opt ? opt->band_chunk : 0;
         }
@@ -1183,9 +1227,13 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
     }
     cmax = std::min<int64_t>(cmax, INT32_MAX / maxg);
     cmax = std::min<int64_t>(cmax, INT32_MAX / h0.grid[2]);
-    // k-points of at least half a chunk get launches of their own; the others
+    // k-points of at least half a chunk, or with planes enough to fill the
+    // resident plane workgroups four times over, get launches of their own
+    // (one segment each: the direct y form of the plane kernel); the others
     // share launches, cut into equal chunks
-    const int64_t own = (cmax + 1) / 2;
+    const int64_t fill = (4LL * std::max(1, E.geo.resident_plane_wgs) + h0.grid[2] - 1) /
+                         h0.grid[2];
+    const int64_t own = std::max<int64_t>(1, std::min<int64_t>((cmax + 1) / 2, fill));
     int64_t shared = 0;
     for (int i = 0; i < nk; ++i)
         if (nbands[i] < own) shared += nbands[i];

@@ -1108,10 +1108,13 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
     const int N1 = CX1 ? CX1 * CX2 : g.N1;
     const int N2 = CY1 ? CY1 * CY2 : g.N2;
     const int ldy = CY1 ? CY1 * CY2 + 1 : g.ldy;
-    const int nxo = g.nxo, hx = g.hmin_mod;
+    // occupied x-planes of the current segment (set again when a plane of
+    // another segment comes up)
+    int nxo = L.seg[0].nxo, hx = L.seg[0].hmin_mod;
+    unsigned long long nxo_magic = L.seg[0].nxo_magic;
     // task / nxo by a 64-bit multiply and shift (exact for tasks < 2^16)
     auto div_nxo = [&](int v) {
-        return (int)(((unsigned long long)(unsigned)v * g.nxo_magic) >> 40);
+        return (int)(((unsigned long long)(unsigned)v * nxo_magic) >> 40);
     };
     // LDS after the plane: the y and x stage twiddles and the occupied columns'
     // k ranges, so that the transform stages issue no vector-memory loads other
@@ -1225,7 +1228,11 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                 pos[i] = sl < sg.nst ? sl_info[sl].w : 0;
             }
         }
-        // the segment's column ranges into LDS (read after the next barrier)
+        // the segment's occupied range and column ranges into LDS (read after
+        // the next barrier)
+        nxo = sg.nxo;
+        hx = sg.hmin_mod;
+        nxo_magic = sg.nxo_magic;
         for (int i = tid; i < nxo; i += nthr) cols[i] = t.cols[sg.col_off + i];
         spos_seg = si;
     };
@@ -2585,7 +2592,7 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
         if constexpr (std::is_same<T, double>::value &&
                       (MODE == MODE_APPLY || MODE == MODE_DENSITY ||
                        MODE == MODE_APPLY_DENSITY)) {
-            const bool dy1 = !W && dyok && g.nxo * g.L2y <= threads;
+            const bool dy1 = !W && dyok && L.seg[0].nxo * g.L2y <= threads;
             if (threads > 512 && plane_codelet_max(g) > 16) return hipErrorInvalidValue;
             if (threads > 768) {
                 if constexpr (DYK && !W)
@@ -2604,7 +2611,7 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
         }
         const int nt = threads < 512 ? threads : 512;
         if constexpr (DYK && !W && std::is_same<T, float>::value)
-            if (dyok && g.nxo * g.L2y <= 2 * nt)
+            if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);
         return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0, G>, nt);
     };
@@ -2797,7 +2804,7 @@ static hipError_t launch_plane_full_lean(const Geometry &g, const DevTables &t, 
     if (g.full != 1) return hipSuccess;
     const bool one = L.nseg == 1;
     if constexpr (std::is_same<T, double>::value) {
-        const bool dy = one && g.nxo * Y2 <= threads;
+        const bool dy = one && L.seg[0].nxo * Y2 <= threads;
         if (threads == 1024)
             return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, false, 1>)
                       : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, false, 0>);
@@ -2805,7 +2812,7 @@ static hipError_t launch_plane_full_lean(const Geometry &g, const DevTables &t, 
             return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 768, false, 1>)
                       : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 768, false, 0>);
     } else {
-        const bool dy = one && g.nxo * Y2 <= 2 * threads;
+        const bool dy = one && L.seg[0].nxo * Y2 <= 2 * threads;
         if (threads == 512)
             return dy ? go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 512, false, 2>)
                       : go(k_plane_full<T, MODE_APPLY, X1, X2, Y1, Y2, ZX, FX, ZY, 512, false, 0>);

@@ -80,6 +80,11 @@ struct Seg {
     int band_lo, nb, blk_lo;
     int nbr;          // real mode: real bands from `in` / `out` (2 nb or 2 nb - 1)
     int hole_off, nholes; // rows of the segment in the hole table
+    // the segment's occupied x-planes (a batch with a whole-plane layout plans
+    // each k-point on its own occupied range): count, ceil(2^40 / count) and
+    // first x-plane mod N1
+    int nxo, hmin_mod;
+    unsigned long long nxo_magic;
 };
 struct Launch {
     int nseg;  // segments in use (1 .. kMaxSeg)

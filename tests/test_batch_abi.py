@@ -35,12 +35,19 @@ def test_members_match_oracle_and_share_layout():
         counts.append((p.npw, st_ref.shape[0]))
     # plane-wave and stick counts of the four shifted spheres
     assert counts == [(24405, 1009), (24408, 1012), (24371, 1015), (24420, 1015)]
+    # whole-plane layout: every member keeps its own occupied x-planes and is
+    # laid out as a stand-alone plan of its k
     lays = [p.layout() for p in b.plans]
-    assert all(l == lays[0] for l in lays)
-    assert lays[0]["nxo"] == 37            # union of the occupied x-planes
-    alone = vloc.Plan(C4["grid"], cell, ecut, C4["kpts"][1])
-    assert alone.layout()["nxo"] == 36     # a stand-alone plan keeps its own range
+    assert [l["nxo"] for l in lays] == [37, 36, 36, 36]
+    assert all(l["plane_xmode"] == 3 for l in lays)
+    for l, k in zip(lays, C4["kpts"]):
+        assert l == vloc.Plan(C4["grid"], cell, ecut, k).layout()
     assert b.info() == dict(nk=4, band_chunk=0, graphs_captured=0, graph_launches=0)
+    # row buffers size LDS by the occupied range: members cover the union
+    br = c4_batch(plane_xmode=1)
+    lays = [p.layout() for p in br.plans]
+    assert all(l == lays[0] for l in lays) and lays[0]["nxo"] == 37
+    assert vloc.Plan(C4["grid"], cell, ecut, C4["kpts"][1], plane_xmode=1).layout()["nxo"] == 36
 
 
 def test_batch_create_validation():

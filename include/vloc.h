@@ -289,7 +289,7 @@ vloc_status vloc_r2g(vloc_plan plan, const void *psi_r, int64_t nbands, void *c_
  * balancing of uneven units, Sec. 3.2, carried to whole k-points; Sec. 1 on
  * aggregating the transforms of many bands).  A k-point with at least half a
  * band chunk of bands, or with enough bands that its z-planes fill the resident
- * plane workgroups four times over, runs in launches of its own (its bands cut
+ * plane workgroups eight times over, runs in launches of its own (its bands cut
  * into equal chunks); the bands of the smaller k-points are concatenated
  * (k-point order) and each chunk of them runs as ONE launch of each kernel,
  * whose workgroups take planes and stick groups of every k-point in it from one

@@ -1228,10 +1228,10 @@ vloc_status vloc_batch_apply(vloc_batch batch, const void *const *c, const int64
     cmax = std::min<int64_t>(cmax, INT32_MAX / maxg);
     cmax = std::min<int64_t>(cmax, INT32_MAX / h0.grid[2]);
     // k-points of at least half a chunk, or with planes enough to fill the
-    // resident plane workgroups four times over, get launches of their own
+    // resident plane workgroups eight times over, get launches of their own
     // (one segment each: the direct y form of the plane kernel); the others
     // share launches, cut into equal chunks
-    const int64_t fill = (4LL * std::max(1, E.geo.resident_plane_wgs) + h0.grid[2] - 1) /
+    const int64_t fill = (8LL * std::max(1, E.geo.resident_plane_wgs) + h0.grid[2] - 1) /
                          h0.grid[2];
     const int64_t own = std::max<int64_t>(1, std::min<int64_t>((cmax + 1) / 2, fill));
     int64_t shared = 0;

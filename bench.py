@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+VECTOR_PEAK = 78.6e12      # FLOP/s, MI355X FP64 vector (and non-packed FP32)
 VECTOR_PEAK = 78.6e12      # FLOP/s: FP64 vector; FP32 without packed instructions runs the same
 
 
@@ -129,7 +130,7 @@ def schedule(grid, cell, ecut, kpts, nbands, precision):
 
 
 def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, keep=False,
-            tuned=True):
+            tuned=True, per_apply=False):
     """Throughput of one plan on a named workload (with its tuned schedule when
     one is stored); optionally a second pass with per-launch events for the
     kernel split."""
@@ -168,6 +169,21 @@ def measure(workload, precision, steps, warmup, gamma=False, kernel_pass=True, k
         kms, kn = plan.read_timing()
         plan.enable_timing(False)
         res.update(ms_step_kernel_pass=ms_k / steps, kms=kms, kn=kn)
+    if per_apply:
+        # one HIP event pair around each apply (a pass of its own)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record(stream)
+            run()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        t = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        res["per_apply_ms"] = {"median": round(float(np.median(t)), 4),
+                               "min": round(float(t.min()), 4),
+                               "max": round(float(t.max()), 4),
+                               "timing": "HIP events around each apply, a pass after the timed region and the per-launch event pass"}
     if keep:
         res.update(out=out, c=c, V=V)
     return res
@@ -336,6 +352,9 @@ def path_figures(r, precision):
     return {"value": round(v, 1), "ms_per_step": round(r["ms_step"], 4),
             "hbm_frac_path": round(sz["b_alg"] * v / HBM_PEAK, 4),
             "flop_rate_tflops": round(sz["f_alg"] * v / 1e12, 2),
+            # FP32 issues at the FP64 rate here (packed FP32 instructions are
+            # not used), so both precisions take the 78.6 TFLOP/s vector peak
+            "flop_frac_vector_peak": round(sz["f_alg"] * v / VECTOR_PEAK, 4),
             "algorithmic_bytes_per_band": round(sz["b_alg"])}
 
 
@@ -390,7 +409,7 @@ def main():
     steps, warmup = args.steps, args.warmup
 
     # ---- headline: 96^3, 256 bands, FP64
-    r = measure("c2_96", "f64", steps, warmup, keep=True)
+    r = measure("c2_96", "f64", steps, warmup, keep=True, per_apply=True)
     head = path_figures(r, "f64")
     split, achieved, k2_bytes, launch_bands, k2_avg_s = kernel_figures(r, steps)
     log(f"# f64: {r['ms_step']:.4f} ms/step ({r['ms_step_kernel_pass']:.4f} with per-launch "
@@ -418,6 +437,8 @@ def main():
                    "bands_per_launch": round(launch_bands, 2), "precision": "f64"},
         "hbm_frac_path": head["hbm_frac_path"],
         "flop_rate_tflops": head["flop_rate_tflops"],
+        "flop_frac_vector_peak": head["flop_frac_vector_peak"],
+        "per_apply_ms": r["per_apply_ms"],
         "roofline": {"bound": "hbm", "kernel": "k_plane (K2)",
                      "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK, 4),
@@ -451,12 +472,13 @@ def main():
                                       "ms_per_step": round(rd["ms_step"], 4)}
         del rd
     # ---- the metric's FP32 column, timed the same way
-    r32 = measure("c2_96", "f32", steps, warmup, keep=True)
+    r32 = measure("c2_96", "f32", steps, warmup, keep=True, per_apply=True)
     f32 = path_figures(r32, "f32")
     s32, a32, b32, lb32, k2s32 = kernel_figures(r32, steps)
     f32["speedup_vs_f64"] = round(r32["bands_per_s"] / head["value"], 3)
     f32["schedule"] = r32["schedule"]
     f32["kernel_ms_per_step"] = s32
+    f32["per_apply_ms"] = r32["per_apply_ms"]
     f32["k2_roofline"] = {"achieved_GBps": round(a32 / 1e9, 1), "frac": round(a32 / HBM_PEAK, 4),
                           "avg_launch_ms": round(k2s32 * 1e3, 4),
                           "algorithmic_bytes_per_launch": round(b32),

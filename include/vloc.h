@@ -94,8 +94,7 @@ typedef struct {
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
     int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where
-                                 the whole plane fits in LDS, else 6 in FP64 and 1
-                                 in FP32); 1 = the
+                                 the whole plane fits in LDS, else 6, else 1); 1 = the
                                  occupied x-planes plus per-wavefront row buffers;
                                  2 = occupied x-planes, one lane quad per x row
                                  (needs N1 in {24, 72, 80, 96} with the matching y

@@ -598,12 +598,12 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     // buffer of N2 / P rows (N1 x (N2 / P + 1)) for the x pass, sharing the
     // LDS; the x pass runs part by part and the rows of the other parts wait
     // in a per-workgroup device scratch of nxo x N2 values.  P divides L1y, so
-    // that the rows of one y stage-B line lie in one part.  The FP64 default
-    // where the whole plane does not fit (measured faster than the row buffers
-    // at 128^3: 768 threads, the only FP64 width with registers for its 16-point
-    // stages); plane_rows asks for N2 / P rows per part.
-    if (p.opt.plane_xmode == 6 ||
-        (p.opt.plane_xmode == 0 && !p.plane_full && p.opt.precision == VLOC_F64)) {
+    // that the rows of one y stage-B line lie in one part.  The default where
+    // the whole plane does not fit (measured faster than the row buffers: FP64
+    // at 128^3 on 768 threads, the only FP64 width with registers for its
+    // 16-point stages; FP32 at 144^3 and 160^3 on 1024); plane_rows asks for
+    // N2 / P rows per part.
+    if (p.opt.plane_xmode == 6 || (p.opt.plane_xmode == 0 && !p.plane_full)) {
         const int nthr = p.opt.plane_threads ? p.opt.plane_threads
                                              : (big_codelet ? 512 : (es == 16 ? 768 : 1024));
         // unless asked otherwise, the longer y codelet first: shorter y

@@ -136,6 +136,25 @@ def test_parted_128_default_layout_vs_oracle():
     assert err.max() <= TOL64
 
 
+def test_parted_144_f32_default_layout_vs_oracle():
+    """The default FP32 layout at 144^3 with the |G| <= 36 sphere: the parted
+    plane on 1024 threads, runtime-sized 12 x 12 lines."""
+    grid, cell, ecut, k = (144, 144, 144), synth.cubic_cell(), 648.0, (0, 0, 0)
+    label(test="parted_144_f32")
+    hkl = oracle.sphere_py(cell, ecut, k)
+    c = synth.coefficients(hkl, 2, k)
+    V = synth.potential(grid, 8)
+    p = vloc.Plan(grid, cell, ecut, k, precision="f32")
+    lay = p.layout()
+    assert lay["plane_xmode"] == 6 and lay["plane_threads"] == 1024
+    got = p.apply(dev(c, torch.complex64), dev(V, torch.float32))
+    torch.cuda.synchronize()
+    err = relerr_per_band(got.cpu().numpy().astype(np.complex128),
+                          reference(grid, cell, ecut, k, c, V, "f32"))
+    print("144^3 f32 parted err", err.max())
+    assert err.max() <= TOL32
+
+
 def test_parted_batch_and_noalloc():
     """A batch of two k-points (two segments in one launch) and the
     allocation-free entry point on a parted plan equal the plain calls."""

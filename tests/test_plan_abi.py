@@ -272,6 +272,9 @@ def test_layout_defaults():
                  dict(plane_xmode=6, plane_rows=32)):
         lay = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, **opts).layout()
         assert lay["plane_xmode"] == 6
+    # FP32 at 144^3 (the whole plane 144 x 145 x 8 B does not fit): parted, 1024 threads
+    lay = vloc.Plan((144, 144, 144), synth.cubic_cell(), 648.0, precision="f32").layout()
+    assert lay["plane_xmode"] == 6 and lay["plane_threads"] == 1024
     rows = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, plane_xmode=1).layout()
     assert rows["plane_xmode"] == 1 and (rows["L1x"], rows["L2x"]) == (8, 16)
     with pytest.raises(vloc.VlocError):

@@ -196,3 +196,28 @@ def test_many_small_kpoints_vs_oracle(precision):
         err = relerr_per_band(o.cpu().numpy().astype(np.complex128), ref)
         print(precision, "k", k, "err", err.max())
         assert err.max() <= tol
+
+
+@pytest.mark.parametrize("xmode", [4, 1])
+def test_layout_variants_in_batches_vs_oracle(xmode):
+    """Batches on the other layouts: rows owned by wavefronts (plane_xmode 4;
+    members on their own occupied ranges, as with the default whole plane) and
+    row buffers (plane_xmode 1; members on the union of the ranges), with one
+    launch holding several k-points (small band counts), against the oracle."""
+    # occupied x-planes of their own: 13, 12, 12 (k shifted by half a cell)
+    kpts = ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.5, 0.5, 0.5))
+    nbs = (2, 3, 1)
+    grid, ecut = (24, 24, 24), 18.0
+    label(test="batch_layouts", xmode=xmode)
+    b = vloc.Batch(grid, CELL, ecut, kpts, plane_xmode=xmode)
+    lays = [p.layout() for p in b.plans]
+    assert all(l["plane_xmode"] == xmode for l in lays)
+    assert [l["nxo"] for l in lays] == ([13, 12, 12] if xmode == 4 else [13, 13, 13])
+    cs, V = inputs(b, nbs, 4, kpts)
+    dc, dV = to_dev(cs, V, "f64")
+    outs = b.apply(dc, dV)
+    torch.cuda.synchronize()
+    for c, o, k, p in zip(cs, outs, kpts, b.plans):
+        ref = oracle.apply(grid, CELL, ecut, k, c, V)
+        assert relerr_per_band(o.cpu().numpy(), ref).max() <= 1e-12
+        assert torch.equal(o, p.apply(torch.from_numpy(c).to("cuda"), dV))

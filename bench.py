@@ -290,7 +290,7 @@ def measure_grad(steps, warmup):
     import torch
 
     import synth
-    from paper_1601_07378_amd import autograd, vloc
+    from paper_1601_07378_amd import autograd, autotune, vloc
 
     w_ = synth.WORKLOADS["c5_128"]
     grid, cell, ecut, nb = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"]), w_["nbands"]
@@ -298,7 +298,9 @@ def measure_grad(steps, warmup):
     for prec in ("f32", "f64"):
         ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
             (torch.complex64, torch.float32)
-        plan = vloc.Plan(grid, cell, ecut, precision=prec)
+        knobs, source = schedule(grid, cell, ecut, [(0.0, 0.0, 0.0)], [nb], prec)
+        plan = vloc.Plan(grid, cell, ecut, precision=prec,
+                         **(autotune.to_options(knobs) if knobs else {}))
         c = torch.from_numpy(synth.coefficients(plan.gvectors(), nb)).to("cuda", ct)
         V = torch.from_numpy(synth.potential(grid, w_["ngauss"])).to("cuda", rt)
         w = torch.from_numpy(synth.band_weights(nb)).to("cuda", torch.float64)
@@ -316,7 +318,8 @@ def measure_grad(steps, warmup):
         warm(step, warmup)
         ms = timed_region(step, steps, stream) / steps
         res[prec] = {"value": round(nb / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
-                     "plane_xmode": plan.layout()["plane_xmode"]}
+                     "plane_xmode": plan.layout()["plane_xmode"],
+                     "schedule": knobs or "planner default", "schedule_source": source}
         del c, V, w, plan
         torch.cuda.empty_cache()
     res["unit"] = "bands/s (energy + all gradients)"

@@ -290,7 +290,7 @@ def measure_grad(steps, warmup):
     import torch
 
     import synth
-    from paper_1601_07378_amd import autograd, autotune, vloc
+    from paper_1601_07378_amd import autograd, vloc
 
     w_ = synth.WORKLOADS["c5_128"]
     grid, cell, ecut, nb = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"]), w_["nbands"]
@@ -298,9 +298,11 @@ def measure_grad(steps, warmup):
     for prec in ("f32", "f64"):
         ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
             (torch.complex64, torch.float32)
-        knobs, source = schedule(grid, cell, ecut, [(0.0, 0.0, 0.0)], [nb], prec)
-        plan = vloc.Plan(grid, cell, ecut, precision=prec,
-                         **(autotune.to_options(knobs) if knobs else {}))
+        # the planner's schedule: the stored 128^3 schedules were tuned on the
+        # application alone, and their splits have compiled kernels for it only
+        # (the density passes of a step would run the runtime-sized kernels)
+        knobs, source = {}, "planner default"
+        plan = vloc.Plan(grid, cell, ecut, precision=prec)
         c = torch.from_numpy(synth.coefficients(plan.gvectors(), nb)).to("cuda", ct)
         V = torch.from_numpy(synth.potential(grid, w_["ngauss"])).to("cuda", rt)
         w = torch.from_numpy(synth.band_weights(nb)).to("cuda", torch.float64)

@@ -2710,6 +2710,7 @@ hipError_t launch_plane_full_mode(const Geometry &g, const DevTables &t, const L
     VLOC_FULL_CASE(12, 8, 8, 12, 0x1F0, 0xE07, 0x38)
     VLOC_FULL_CASE(8, 9, 8, 12, 0x38, 0xC3, 0x3C)
     VLOC_FULL_CASE(8, 16, 8, 16, 0x38, 0xC3, 0x38)
+    VLOC_FULL_CASE(8, 16, 16, 8, 0x38, 0xC3, 0xFE0)
     VLOC_FULL_CASE(8, 10, 8, 10, 0x38, 0xC3, 0x38)
     VLOC_FULL_CASE(4, 6, 4, 6, 0x4, 0x9, 0x4)
 #undef VLOC_FULL_CASE

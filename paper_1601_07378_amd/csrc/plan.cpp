@@ -592,6 +592,19 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
             p.plane_lds = (int32_t)full_bytes;
             p.plane_threads = p.opt.plane_threads ? p.opt.plane_threads
                                                   : (es == 16 && !big_codelet ? 1024 : 512);
+            // The direct y form of the plane kernel holds nxo L2y y stage-A
+            // tasks, one per thread in FP64 (more than 512 threads), two in FP32.
+            // Unless the y split was asked for, take the swapped split when
+            // only it fits (128^3 FP32, |G| <= 32: 65 x 16 tasks do not fit
+            // 1024, 65 x 8 do); the form saves the scatter, the gather and
+            // three barriers per plane.
+            const int64_t dcap = es == 16 ? (p.plane_threads > 512 ? p.plane_threads : 0)
+                                          : 2LL * p.plane_threads;
+            if (!p.opt.split[1] && dcap > 0 && p.sy.L1 != p.sy.L2 &&
+                (int64_t)p.nxo * p.sy.L2 > dcap && (int64_t)p.nxo * p.sy.L1 <= dcap) {
+                std::swap(p.sy.L1, p.sy.L2);
+                p.zy = zero_mask(p.sy, p.kmin, p.kmax);
+            }
         }
     }
     // Parted plane: the occupied columns (nxo x N2) for the y pass and one row

@@ -262,9 +262,14 @@ def test_direct_y_form_equals_scatter_form(precision, direct, scatter):
     grid, cell, ecut, k, nb = (96, 96, 96), synth.cubic_cell(), 288.0, (0, 0, 0), 3
     label(test="direct_y", precision=precision)
     hkl, c, V = case(grid, cell, ecut, k, nb)
-    pd = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=direct)
-    ps = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=scatter)
+    # the y split given explicitly (8 x 12): otherwise the planner would swap it
+    # for the smaller workgroup, so that its y tasks fit the direct form too
+    pd = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=direct,
+                   split=(0, 8, 0))
+    ps = vloc.Plan(grid, cell, ecut, k, precision=precision, plane_threads=scatter,
+                   split=(0, 8, 0))
     assert pd.layout()["plane_xmode"] == ps.layout()["plane_xmode"] == 3
+    assert pd.layout()["L2y"] == ps.layout()["L2y"] == 12
     got_d, got_s = run(pd, c, V), run(ps, c, V)
     assert np.array_equal(got_d, got_s)
     if precision == "f64":

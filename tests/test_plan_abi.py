@@ -279,8 +279,13 @@ def test_layout_defaults():
     assert rows["plane_xmode"] == 1 and (rows["L1x"], rows["L2x"]) == (8, 16)
     with pytest.raises(vloc.VlocError):
         vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, plane_xmode=3)
-    assert vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0,
-                     precision="f32").layout()["plane_xmode"] == 3
+    l32 = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, precision="f32").layout()
+    # the whole plane; y split 16 x 8 so that the 65 x 8 y stage-A tasks fit the
+    # direct y form (65 x 16 would not)
+    assert l32["plane_xmode"] == 3 and (l32["L1y"], l32["L2y"]) == (16, 8)
+    l32s = vloc.Plan((128, 128, 128), synth.cubic_cell(), 512.0, precision="f32",
+                     split=(0, 8, 0)).layout()
+    assert (l32s["L1y"], l32s["L2y"]) == (8, 16)  # an explicit split is kept
     pq = vloc.Plan((96, 96, 96), synth.cubic_cell(), 288.0, plane_xmode=2)
     assert pq.layout()["plane_xmode"] == 2 and pq.layout()["plane_lds_bytes"] == 49 * 97 * 16
     with pytest.raises(vloc.VlocError):

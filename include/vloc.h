@@ -88,9 +88,10 @@ typedef struct {
                                  kernel (plane_xmode 1), rows per part N2 / P
                                  (plane_xmode 6); 0 = automatic                    */
     int32_t plane_threads;    /* threads per plane workgroup (64..512, multiple of
-                                 64; FP64 plans up to 1024 for vloc_apply and
-                                 vloc_density, parted planes up to 1024 for every
-                                 call); 0 = automatic                              */
+                                 64; FP64 plans up to 1024); 0 = automatic (the
+                                 planner's choices include 1024 for the FP64 whole
+                                 plane, 768 for the FP64 parted plane and 1024 for
+                                 the FP32 parted plane)                            */
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
     int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where

@@ -395,6 +395,9 @@ def main():
                     help="the 96^3 FP64 and FP32 legs only (profiling runs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the M0, real-mode, batch and gradient legs")
+    ap.add_argument("--only-grad", action="store_true",
+                    help="the 128^3 energy + gradient leg only, its figures as the one "
+                         "JSON line (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of 256 MiB so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -412,6 +415,13 @@ def main():
     from paper_1601_07378_amd import autotune
     log(f"# device: {torch.cuda.get_device_name(0)} ({autotune.device_tag()})")
     steps, warmup = args.steps, args.warmup
+    if args.only_grad:
+        rg = measure_grad(steps, warmup)
+        log(f"# energy + gradients 128^3 x 512: f32 {rg['f32']['value']:,.0f} bands/s, "
+            f"f64 {rg['f64']['value']:,.0f} bands/s")
+        print(json.dumps({"differentiable_energy": rg, "steps": steps, "warmup": warmup}),
+              flush=True)
+        return
 
     # ---- headline: 96^3, 256 bands, FP64
     r = measure("c2_96", "f64", steps, warmup, keep=True, per_apply=True)

@@ -1094,7 +1094,7 @@ __global__ __launch_bounds__(1024) void k_plane_wide(Geometry g, DevTables t, La
 // may hold stale values: they are never read as input.  The potential comes
 // pre-arranged as VT[z][x][yp] (yp = position of row y after the y pass).
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
-          bool WPR, int YT, int MR>
+          bool WPR, int YT, int MR, int DA = 0>
 __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTables &t,
                                                 const Launch &L, cx<T> *__restrict__ S,
                                                 const T *__restrict__ VT,
@@ -1178,6 +1178,19 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
         }
     };
     auto seg_of = [&](int bb) { return DENS ? 0 : seg_index_by_band(L, bb); };
+    // DA > 0 (density modes, compiled x split, at most DA x stage-B tasks per
+    // thread): a thread's stage-B tasks are the same (k1, yp) on every plane,
+    // so it sums w_b |psi_b|^2 over the bands of a work item in registers and
+    // adds the sums to the item's partial plane once, when the item ends,
+    // instead of a read-modify-write of the partial plane per band
+    constexpr bool DAC = DA > 0 && DENS && !WPR && CX2 > 0;
+    constexpr int NDA = DAC ? DA : 1;
+    constexpr int RDA = DAC ? CX2 : 1;
+    double dacc[NDA][RDA];
+#pragma unroll
+    for (int u = 0; u < NDA; ++u)
+#pragma unroll
+        for (int k2 = 0; k2 < RDA; ++k2) dacc[u][k2] = 0.0;
     // Direct y stage A (launches of one segment, at most YT y tasks per
     // thread): the forward pass takes its stage-A inputs straight from the
     // prefetched stick values and the reverse pass stores its stage-A' outputs
@@ -1383,7 +1396,27 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             for (int k1 = 0; k1 < R; ++k1) row[L2x * k1 * ldy] = mk<T>(xr[k1], xi[k1]);
         });
     };
-    auto stage_b = [&](int k1, int yp) {
+    // w_b |psi_b|^2 of one stage-B task (x = k1 + L1x k2, row yp) into the
+    // registers of the thread's task u, or straight into the partial plane
+    auto add_density = [&](auto RC, const T *xr, const T *xi, int k1, int yp, int u) {
+        constexpr int R = decltype(RC)::value;
+        const double wb = t.wts[band0 + bl];
+        if constexpr (DAC) {
+#pragma unroll
+            for (int k2 = 0; k2 < RDA; ++k2) {
+                const double a = (double)xr[k2], b = (double)xi[k2];
+                dacc[u][k2] += wb * (a * a + b * b);
+            }
+        } else {
+            double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                const double a = (double)xr[k2], b = (double)xi[k2];
+                acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+            }
+        }
+    };
+    auto stage_b = [&](int k1, int yp, int u) {
         with_size<CX2, MR>(L2x, [&](auto RC) {
             constexpr int R = decltype(RC)::value;
             cx<T> *row = plane + L2x * k1 * ldy + yp;
@@ -1419,23 +1452,9 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
 #pragma unroll
                 for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
             } else if (MODE == MODE_DENSITY) {
-                const double wb = t.wts[band0 + bl];
-                double *acc = accz + (long long)k1 * N2 + yp;
-#pragma unroll
-                for (int k2 = 0; k2 < R; ++k2) {
-                    const double a = (double)xr[k2], b = (double)xi[k2];
-                    acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
-                }
+                add_density(RC, xr, xi, k1, yp, u);
             } else {
-                if (MODE == MODE_APPLY_DENSITY) {
-                    const double wb = t.wts[band0 + bl];
-                    double *acc = accz + (long long)k1 * N2 + yp;
-#pragma unroll
-                    for (int k2 = 0; k2 < R; ++k2) {
-                        const double a = (double)xr[k2], b = (double)xi[k2];
-                        acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
-                    }
-                }
+                if (MODE == MODE_APPLY_DENSITY) add_density(RC, xr, xi, k1, yp, u);
                 if (POT) {
 #pragma unroll
                     for (int k2 = 0; k2 < R; ++k2) {
@@ -1493,7 +1512,8 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
                     stage_a(task / nr, y0 + task % nr);
                 wave_sync();
             }
-            for (int task = lane; task < nr * L1x; task += 64) stage_b(task / nr, y0 + task % nr);
+            for (int task = lane; task < nr * L1x; task += 64)
+                stage_b(task / nr, y0 + task % nr, 0);
             wave_sync();
             if (!XPASS_ONLY_FWD) {
                 for (int task = lane; task < nr * L2x; task += 64)
@@ -1510,7 +1530,31 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
             for (int task = tid; task < L2x * N2; task += nthr) stage_a(task / N2, task % N2);
             __syncthreads();
         }
-        for (int task = tid; task < L1x * N2; task += nthr) stage_b(task / N2, task % N2);
+        if constexpr (DAC) {
+            // the thread's tasks u (at most NDA, checked by the launcher); the
+            // sums go to the partial plane when the next plane is another item's
+#pragma unroll
+            for (int u = 0; u < NDA; ++u) {
+                const int task = tid + u * nthr;
+                if (task < L1x * N2) stage_b(task / N2, task % N2, u);
+            }
+            int jn = jc, kn = kc;
+            if (!advance(jn, kn) || jn != jc) {
+#pragma unroll
+                for (int u = 0; u < NDA; ++u) {
+                    const int task = tid + u * nthr;
+                    if (task >= L1x * N2) continue;
+                    double *acc = accz + (long long)(task / N2) * N2 + task % N2;
+#pragma unroll
+                    for (int k2 = 0; k2 < RDA; ++k2) {
+                        acc[(long long)L1x * k2 * N2] += dacc[u][k2];
+                        dacc[u][k2] = 0.0;
+                    }
+                }
+            }
+        } else {
+            for (int task = tid; task < L1x * N2; task += nthr) stage_b(task / N2, task % N2, 0);
+        }
         // the next plane's stick values: issued after the potential's loads, so
         // their latency hides behind the reverse stages
         prefetch_next();
@@ -1601,8 +1645,10 @@ __device__ __forceinline__ void plane_full_body(const Geometry &g, const DevTabl
 // scatter form does not carry its registers)
 // GMR > 0: the runtime-sized kernel compiled for line codelets of at most
 // GMR points only
+// DA > 0: density sums in registers over the x stage-B tasks of a thread (at
+// most DA of them)
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT, bool WPR, int YT, int GMR = 0>
+          int MAXT, bool WPR, int YT, int GMR = 0, int DA = 0>
 __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, Launch L,
                                                      cx<T> *__restrict__ S,
                                                      const T *__restrict__ VT,
@@ -1610,7 +1656,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
 {
     // prefetched slots per thread cover 2048 slots
     plane_full_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT, WPR, YT,
-                    (GMR ? GMR : (MAXT > 512 ? 16 : 32))>(g, t, L, S, VT, psi, band0);
+                    (GMR ? GMR : (MAXT > 512 ? 16 : 32)), DA>(g, t, L, S, VT, psi, band0);
 }
 
 // ------------------------------------------------------- K2, parted plane
@@ -2610,6 +2656,23 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
             }
         }
         const int nt = threads < 512 ? threads : 512;
+        // FP32 density with a plane that leaves one workgroup per CU (so 256
+        // registers per thread) and at most two x stage-B tasks per thread:
+        // the density sums stay in registers over the bands of a work item.
+        // The fused application + density takes the scatter y form there: with
+        // the direct form's prefetch registers as well it would spill.
+        constexpr bool DAK = std::is_same<T, float>::value &&
+                             (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY) && X1 > 0 &&
+                             Y1 > 0 && 8LL * X1 * X2 * Y1 * Y2 > 80 * 1024 && X1 * Y1 * Y2 <= 1024;
+        if constexpr (DAK && !W)
+            if (2LL * lds > 160 * 1024 && X1 * Y1 * Y2 <= 2 * nt) {
+                if constexpr (MODE == MODE_DENSITY)
+                    if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
+                        return go(
+                            k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G, 2>,
+                            nt);
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0, G, 2>, nt);
+            }
         if constexpr (DYK && !W && std::is_same<T, float>::value)
             if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);

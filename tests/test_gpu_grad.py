@@ -143,6 +143,46 @@ def test_apply_density_one_pass(precision, name, grid, cell, ecut, k, nb):
     assert torch.equal(scaled, 4.0 * rho)
 
 
+def test_density_register_sums_128_f32():
+    """FP32 density at 128^3 (|G| <= 32), where the whole plane leaves one
+    512-thread workgroup per CU and each thread keeps the density sums of a
+    work item (one z-plane, one band subset) in registers: 7 bands in launches
+    of 5 and 2 (subsets of 3 + 2 bands, then 1 + 1) against the oracle; the
+    fused application + density equals the separate calls, and 256-thread
+    workgroups (per-band sums into the partial plane, another y layout, so
+    psi differs by FP32 rounding) agree to the FP32 level."""
+    grid, cell, ecut = (128, 128, 128), synth.cubic_cell(), 512.0
+    label(test="density_registers_128_f32")
+    hkl = oracle.sphere_py(cell, ecut)
+    nb = 7
+    c = synth.coefficients(hkl, nb).astype(np.complex64).astype(np.complex128)
+    V = synth.potential(grid, 8).astype(np.float32).astype(np.float64)
+    w = synth.band_weights(nb)
+    plan = vloc.Plan(grid, cell, ecut, precision="f32", band_chunk=5)
+    lay = plan.layout()
+    assert lay["plane_xmode"] == 3 and lay["plane_threads"] == 512
+    assert (lay["L1x"], lay["L2x"]) == (8, 16) and lay["plane_lds_bytes"] > 80 * 1024
+    tc = torch.from_numpy(c).to("cuda", torch.complex64)
+    tV = torch.from_numpy(V).to("cuda", torch.float32)
+    tw = torch.from_numpy(w).cuda()
+    rho = plan.density(tc, tw)
+    out, rho2 = plan.apply_density(tc, tV, tw)
+    ref_out = plan.apply(tc, tV)
+    p256 = vloc.Plan(grid, cell, ecut, precision="f32", band_chunk=5, plane_threads=256)
+    assert p256.layout()["plane_threads"] == 256
+    rho3 = p256.density(tc, tw)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_out)
+    assert relerr(rho2.cpu().numpy(), rho.cpu().numpy()) <= 1e-15
+    psi = oracle.g2r(grid, cell, ecut, (0, 0, 0), c).reshape(nb, -1)
+    rho_or = (w[:, None] * np.abs(psi) ** 2).sum(0) / np.prod(grid)
+    err = relerr(rho.cpu().numpy().ravel(), rho_or)
+    err3 = relerr(rho3.cpu().numpy().ravel(), rho_or)
+    print("128^3 f32 density err: register sums", err, "per-band sums", err3)
+    assert err <= 3e-6 and err3 <= 3e-6
+    assert relerr(rho3.cpu().numpy(), rho.cpu().numpy()) <= 1e-6
+
+
 def _energy(plan, c, V, w):
     with torch.no_grad():
         return ag.local_energy(plan, c, V, w).item()

@@ -1680,7 +1680,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_full(Geometry g, DevTables t, La
 // scattered into C and gathered back).  The stage arithmetic is that of the
 // whole-plane kernel.
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY, int PF,
-          int MR>
+          int MR, int DA = 0>
 __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTables &t,
                                                  const Launch &L, cx<T> *__restrict__ S,
                                                  const T *__restrict__ VT,
@@ -1799,6 +1799,22 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
         prefetch(zz, bb);
     }
     constexpr bool XPASS_ONLY_FWD = (MODE == MODE_G2R || MODE == MODE_DENSITY);
+    // DA > 0 (density modes, compiled splits, P = DA parts of at most one x
+    // stage-B task per thread): the thread's stage-B task of each part is the
+    // same on every plane, so the density sums of a work item stay in
+    // registers, the part in progress in dacc[0] (the array rotates by one
+    // after each part) and go to the partial plane when the item ends.  These
+    // kernels run 512 threads (256 registers each), so the y stage-B lines
+    // held across a barrier may take a second round (TWO).
+    constexpr bool DAC = DA > 0 && DENS && CX2 > 0;
+    constexpr bool TWO = DAC;
+    constexpr int NDA = DAC ? DA : 1;
+    constexpr int RDA = DAC ? CX2 : 1;
+    double dacc[NDA][RDA];
+#pragma unroll
+    for (int u = 0; u < NDA; ++u)
+#pragma unroll
+        for (int k2 = 0; k2 < RDA; ++k2) dacc[u][k2] = 0.0;
 
     for (; have; have = advance(jc, kc)) {
     int z, bl;
@@ -1878,12 +1894,26 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
             const int k1 = div_nxo(task), hc = task - k1 * nxo;
             T xr[R], xi[R];
             if (act) line(hc, k1, xr, xi);
+            // second round (TWO): line tid + nthr
+            constexpr int R2 = TWO ? R : 1;
+            const int tb = tid + nthr;
+            const bool actb = TWO && tb < nxo * k1r;
+            const int k1b = div_nxo(tb), hcb = tb - k1b * nxo;
+            T yr[R2], yi[R2];
+            if constexpr (TWO)
+                if (actb) line(hcb, k1b, yr, yi);
             __syncthreads();
             if (act) {
                 cx<T> *dst = buf + col_of(hc) * ldr + L2y * k1;
 #pragma unroll
                 for (int k2 = 0; k2 < R; ++k2) dst[k2] = mk<T>(xr[k2], xi[k2]);
             }
+            if constexpr (TWO)
+                if (actb) {
+                    cx<T> *dst = buf + col_of(hcb) * ldr + L2y * k1b;
+#pragma unroll
+                    for (int k2 = 0; k2 < R; ++k2) dst[k2] = mk<T>(yr[k2], yi[k2]);
+                }
         });
         __syncthreads();
     }
@@ -1891,6 +1921,26 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
     // x pass, part by part: stage_a forward stage A of row yp (= yb + r) for
     // n2; stage_b stage B for k1 with the potential, the density or the
     // real-space values; stage_a2 reverse stage A', occupied outputs only
+    // w_b |psi_b|^2 of one stage-B task into the registers of the part in
+    // progress, or straight into the partial plane
+    auto add_density = [&](auto RC, const T *xr, const T *xi, int k1, int yp) {
+        constexpr int R = decltype(RC)::value;
+        const double wb = t.wts[band0 + bl];
+        if constexpr (DAC) {
+#pragma unroll
+            for (int k2 = 0; k2 < RDA; ++k2) {
+                const double a = (double)xr[k2], b = (double)xi[k2];
+                dacc[0][k2] += wb * (a * a + b * b);
+            }
+        } else {
+            double *acc = accz + (long long)k1 * N2 + yp;
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                const double a = (double)xr[k2], b = (double)xi[k2];
+                acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
+            }
+        }
+    };
     for (int part = 0; part < P; ++part) {
         const int yb = part * rpp;
         const bool first = part == 0, last = part == P - 1;
@@ -1961,23 +2011,9 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
 #pragma unroll
                     for (int k2 = 0; k2 < R; ++k2) dst[L1x * k2] = mk<T>(xr[k2], xi[k2]);
                 } else if (MODE == MODE_DENSITY) {
-                    const double wb = t.wts[band0 + bl];
-                    double *acc = accz + (long long)k1 * N2 + yp;
-#pragma unroll
-                    for (int k2 = 0; k2 < R; ++k2) {
-                        const double a = (double)xr[k2], b = (double)xi[k2];
-                        acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
-                    }
+                    add_density(RC, xr, xi, k1, yp);
                 } else {
-                    if (MODE == MODE_APPLY_DENSITY) {
-                        const double wb = t.wts[band0 + bl];
-                        double *acc = accz + (long long)k1 * N2 + yp;
-#pragma unroll
-                        for (int k2 = 0; k2 < R; ++k2) {
-                            const double a = (double)xr[k2], b = (double)xi[k2];
-                            acc[(long long)L1x * k2 * N2] += wb * (a * a + b * b);
-                        }
-                    }
+                    if (MODE == MODE_APPLY_DENSITY) add_density(RC, xr, xi, k1, yp);
                     if (POT) {
 #pragma unroll
                         for (int k2 = 0; k2 < R; ++k2) {
@@ -1991,6 +2027,15 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
                 }
             }
         });
+        if constexpr (DAC && NDA > 1) {
+#pragma unroll
+            for (int k2 = 0; k2 < RDA; ++k2) {
+                const double d0 = dacc[0][k2];
+#pragma unroll
+                for (int u = 0; u + 1 < NDA; ++u) dacc[u][k2] = dacc[u + 1][k2];
+                dacc[NDA - 1][k2] = d0;
+            }
+        }
         if (last && MODE != MODE_R2G) {
             // the next plane's stick values, issued after the potential's loads
             int jn = jc, kn = kc, zz, bb;
@@ -2030,6 +2075,22 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
         });
         __syncthreads();
     }
+    if constexpr (DAC) {
+        // the item's sums to its partial plane when the next plane is another item's
+        int jn = jc, kn = kc;
+        if ((!advance(jn, kn) || jn != jc) && tid < L1x * rpp) {
+            const int k1 = tid / rpp, r = tid - k1 * rpp;
+#pragma unroll
+            for (int u = 0; u < NDA; ++u) {
+                double *acc = accz + (long long)k1 * N2 + u * rpp + r;
+#pragma unroll
+                for (int k2 = 0; k2 < RDA; ++k2) {
+                    acc[(long long)L1x * k2 * N2] += dacc[u][k2];
+                    dacc[u][k2] = 0.0;
+                }
+            }
+        }
+    }
     if (XPASS_ONLY_FWD) continue;
     // y reverse, stage B', then C rebuilt (it overlaps R): the lines of the
     // last part read R before a barrier (one round, nxo L1y / P tasks), the
@@ -2056,8 +2117,26 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
                 xi[k2] = v.y;
             }
         }
+        // second round (TWO): line tid + nthr
+        constexpr int R2 = TWO ? R : 1;
+        const int tb = tid + nthr;
+        const bool actb = TWO && tb < nxo * (L1y - k1l);
+        const int k1b = k1l + div_nxo(tb), hcb = tb - (k1b - k1l) * nxo;
+        T yr2[R2], yi2[R2];
+        if constexpr (TWO)
+            if (actb) {
+                const cx<T> *src = buf + col_of(hcb) * ldr + (L2y * k1b - (P - 1) * rpp);
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) {
+                    cx<T> v = src[k2];
+                    yr2[k2] = v.x;
+                    yi2[k2] = v.y;
+                }
+            }
         __syncthreads();
         if (act) put(hc, k1, xr, xi);
+        if constexpr (TWO)
+            if (actb) put(hcb, k1b, yr2, yi2);
         for (int tg = tid; tg < nxo * k1l; tg += nthr) {
             const int k1g = div_nxo(tg), hcg = tg - k1g * nxo;
             const cx<T> *src = G + (long long)hcg * N2 + L2y * k1g;
@@ -2106,8 +2185,10 @@ __device__ __forceinline__ void plane_parts_body(const Geometry &g, const DevTab
     }
 }
 
+// DA > 0: density sums in registers over DA parts (one x stage-B task per
+// thread and part)
 template <typename T, int MODE, int CX1, int CX2, int CY1, int CY2, int ZX, int FX, int ZY,
-          int MAXT, int GMR = 0>
+          int MAXT, int GMR = 0, int DA = 0>
 __global__ __launch_bounds__(MAXT) void k_plane_parts(Geometry g, DevTables t, Launch L,
                                                       cx<T> *__restrict__ S,
                                                       const T *__restrict__ VT,
@@ -2115,7 +2196,7 @@ __global__ __launch_bounds__(MAXT) void k_plane_parts(Geometry g, DevTables t, L
 {
     // prefetched slots per thread cover 2048 slots
     plane_parts_body<T, MODE, CX1, CX2, CY1, CY2, ZX, FX, ZY, (2048 + MAXT - 1) / MAXT,
-                     (GMR ? GMR : (MAXT > 512 ? 16 : 32))>(g, t, L, S, VT, psi, band0);
+                     (GMR ? GMR : (MAXT > 512 ? 16 : 32)), DA>(g, t, L, S, VT, psi, band0);
 }
 
 // ------------------------------------------------------- K2, row blocks
@@ -2729,6 +2810,24 @@ static hipError_t launch_plane_parts(const Geometry &g, const DevTables &t, cons
                            reinterpret_cast<cx<T> *>(psi), (long long)band0);
         return hipGetLastError();
     };
+    // FP64 density, x split 8 x 16, y split 16 x 8, two parts: the density sums
+    // stay in registers over a work item (512 threads, so 256 registers per
+    // thread; one x stage-B task per thread and part, the held y stage-B lines
+    // in at most two rounds)
+    if constexpr (std::is_same<T, double>::value &&
+                  (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY)) {
+        if (g.L1x == 8 && g.L2x == 16 && g.L1y == 16 && g.L2y == 8 && (g.zx & 0x38) == 0x38 &&
+            (g.fx & 0xC3) == 0xC3 && (g.zy & 0xFE0) == 0xFE0 && g.parts == 2 && threads >= 512 &&
+            8 * (g.N2 / 2) <= 512 && g.nxo * (16 / 2) <= 2 * 512) {
+            auto kern = k_plane_parts<T, MODE, 8, 16, 16, 8, 0x38, 0xC3, 0xFE0, 512, 0, 2>;
+            hipError_t e = allow_lds(kern, (size_t)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3(plane_blocks(g, L.nbt)), dim3(512), (size_t)lds, st, g,
+                               t, L, reinterpret_cast<cx<T> *>(S), reinterpret_cast<const T *>(V),
+                               reinterpret_cast<cx<T> *>(psi), (long long)band0);
+            return hipGetLastError();
+        }
+    }
 #define VLOC_PARTS_CASE(X1, X2, Y1, Y2, ZX, FX, ZY)                                                \
     if (g.L1x == X1 && g.L2x == X2 && g.L1y == Y1 && g.L2y == Y2 && (g.zx & ZX) == ZX &&          \
         (g.fx & FX) == FX && (g.zy & ZY) == ZY)                                                   \

@@ -183,6 +183,45 @@ def test_density_register_sums_128_f32():
     assert relerr(rho3.cpu().numpy(), rho.cpu().numpy()) <= 1e-6
 
 
+def test_density_register_sums_128_f64_parted():
+    """FP64 density at 128^3 (|G| <= 32) on the parted plane (two parts of 64
+    rows): the density kernels run 512 threads and keep the sums of a work
+    item in registers, one x stage-B task per thread and part.  7 bands in
+    launches of 5 and 2 against the oracle (1e-12); the fused application +
+    density equals the separate calls; a 256-thread plan (the row-buffer
+    layout, per-band sums into the partial plane) agrees to rounding."""
+    grid, cell, ecut = (128, 128, 128), synth.cubic_cell(), 512.0
+    label(test="density_registers_128_f64")
+    hkl = oracle.sphere_py(cell, ecut)
+    nb = 7
+    c = synth.coefficients(hkl, nb)
+    V = synth.potential(grid, 8)
+    w = synth.band_weights(nb)
+    plan = vloc.Plan(grid, cell, ecut, band_chunk=5)
+    lay = plan.layout()
+    assert lay["plane_xmode"] == 6 and lay["plane_rows"] == 64
+    assert (lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"]) == (8, 16, 16, 8)
+    tc = torch.from_numpy(c).cuda()
+    tV = torch.from_numpy(V).cuda()
+    tw = torch.from_numpy(w).cuda()
+    rho = plan.density(tc, tw)
+    out, rho2 = plan.apply_density(tc, tV, tw)
+    ref_out = plan.apply(tc, tV)
+    p256 = vloc.Plan(grid, cell, ecut, band_chunk=5, plane_threads=256)
+    assert p256.layout()["plane_threads"] == 256 and p256.layout()["plane_xmode"] == 1
+    rho3 = p256.density(tc, tw)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_out)
+    assert relerr(rho2.cpu().numpy(), rho.cpu().numpy()) <= 1e-15
+    psi = oracle.g2r(grid, cell, ecut, (0, 0, 0), c).reshape(nb, -1)
+    rho_or = (w[:, None] * np.abs(psi) ** 2).sum(0) / np.prod(grid)
+    err = relerr(rho.cpu().numpy().ravel(), rho_or)
+    err3 = relerr(rho3.cpu().numpy().ravel(), rho_or)
+    print("128^3 f64 density err: register sums", err, "per-band sums", err3)
+    assert err <= 1e-12 and err3 <= 1e-12
+    assert relerr(rho3.cpu().numpy(), rho.cpu().numpy()) <= 1e-13
+
+
 def _energy(plan, c, V, w):
     with torch.no_grad():
         return ag.local_energy(plan, c, V, w).item()

@@ -91,7 +91,12 @@ typedef struct {
                                  64; FP64 plans up to 1024); 0 = automatic (the
                                  planner's choices include 1024 for the FP64 whole
                                  plane, 768 for the FP64 parted plane and 1024 for
-                                 the FP32 parted plane)                            */
+                                 the FP32 parted plane).  The density kernels may
+                                 run fewer, to hold a work item's density sums in
+                                 registers: 512 for the FP64 parted plane with x
+                                 split 8 x 16, y split 16 x 8 and two parts (when
+                                 plane_threads >= 512), and at most 512 for the
+                                 FP32 whole plane where it fills a CU's LDS      */
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
     int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where

@@ -143,25 +143,29 @@ def test_apply_density_one_pass(precision, name, grid, cell, ecut, k, nb):
     assert torch.equal(scaled, 4.0 * rho)
 
 
-def test_density_register_sums_128_f32():
+@pytest.mark.parametrize("ysplit", [0, 8])
+def test_density_register_sums_128_f32(ysplit):
     """FP32 density at 128^3 (|G| <= 32), where the whole plane leaves one
     512-thread workgroup per CU and each thread keeps the density sums of a
     work item (one z-plane, one band subset) in registers: 7 bands in launches
     of 5 and 2 (subsets of 3 + 2 bands, then 1 + 1) against the oracle; the
     fused application + density equals the separate calls, and 256-thread
     workgroups (per-band sums into the partial plane, another y layout, so
-    psi differs by FP32 rounding) agree to the FP32 level."""
+    psi differs by FP32 rounding) agree to the FP32 level.  Both compiled y
+    splits: 16 x 8 (the density-only pass in the direct y form) and 8 x 16
+    (scatter form throughout)."""
     grid, cell, ecut = (128, 128, 128), synth.cubic_cell(), 512.0
-    label(test="density_registers_128_f32")
+    label(test="density_registers_128_f32", ysplit=ysplit)
     hkl = oracle.sphere_py(cell, ecut)
     nb = 7
     c = synth.coefficients(hkl, nb).astype(np.complex64).astype(np.complex128)
     V = synth.potential(grid, 8).astype(np.float32).astype(np.float64)
     w = synth.band_weights(nb)
-    plan = vloc.Plan(grid, cell, ecut, precision="f32", band_chunk=5)
+    plan = vloc.Plan(grid, cell, ecut, precision="f32", band_chunk=5, split=(0, ysplit, 0))
     lay = plan.layout()
     assert lay["plane_xmode"] == 3 and lay["plane_threads"] == 512
     assert (lay["L1x"], lay["L2x"]) == (8, 16) and lay["plane_lds_bytes"] > 80 * 1024
+    assert lay["L1y"] == (ysplit or 16)
     tc = torch.from_numpy(c).to("cuda", torch.complex64)
     tV = torch.from_numpy(V).to("cuda", torch.float32)
     tw = torch.from_numpy(w).cuda()

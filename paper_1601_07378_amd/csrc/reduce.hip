@@ -79,7 +79,11 @@ __device__ double block_sum_256(double v, double *sh)
     return sh[0];
 }
 
-// out[n] = Re sum_g conj(a[n][g]) b[n][g]: one block per band, FP64.
+// out[n] = Re sum_g conj(a[n][g]) b[n][g]: one block per band, FP64.  Each
+// thread keeps four partial sums (coefficients g, g + 256, g + 512, g + 768 of
+// each 1024-wide step), so that eight loads are in flight per thread instead of
+// one dependent chain; the partial sums and the block tree combine in a fixed
+// order (the result does not depend on timing).
 template <typename T>
 __global__ __launch_bounds__(256) void k_band_dot(const typename Cplx<T>::type *__restrict__ a,
                                                   const typename Cplx<T>::type *__restrict__ b,
@@ -87,13 +91,32 @@ __global__ __launch_bounds__(256) void k_band_dot(const typename Cplx<T>::type *
 {
     __shared__ double sh[256];
     const long long base = (long long)blockIdx.x * npw;
-    double acc = 0.0;
-    for (long long g = threadIdx.x; g < npw; g += 256) {
-        const auto x = a[base + g];
-        const auto y = b[base + g];
-        acc += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+    const auto *pa = a + base;
+    const auto *pb = b + base;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    long long g = threadIdx.x;
+    for (; g + 768 < npw; g += 1024) {
+        typename Cplx<T>::type x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = pa[g + 256 * u];
+            y[u] = pb[g + 256 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc[u] += (double)x[u].x * (double)y[u].x + (double)x[u].y * (double)y[u].y;
     }
-    const double s = block_sum_256(acc, sh);
+    // at most three coefficients remain
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const long long gu = g + 256 * u;
+        if (gu < npw) {
+            const auto x = pa[gu];
+            const auto y = pb[gu];
+            acc[u] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+        }
+    }
+    const double s = block_sum_256((acc[0] + acc[1]) + (acc[2] + acc[3]), sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
@@ -109,24 +132,32 @@ __global__ __launch_bounds__(256) void k_weighted_sum(const double *__restrict__
     if (threadIdx.x == 0) out[0] = s;
 }
 
-// y[n][g] = factor * scale * w[n] * x[n][g] (w, scale may be NULL = 1).
+// y[n][g] = factor * scale * w[n] * x[n][g] (w, scale may be NULL = 1).  Block
+// b covers 1024 coefficients of band b / bpb (bpb blocks per band): the band
+// and its factor are uniform per block, and each thread moves four elements.
 template <typename T>
-__global__ void k_scale_bands(const typename Cplx<T>::type *__restrict__ x, long long npw,
-                              long long nb, const double *__restrict__ w,
-                              const double *__restrict__ scale, double factor,
-                              typename Cplx<T>::type *__restrict__ y)
+__global__ __launch_bounds__(256) void k_scale_bands(const typename Cplx<T>::type *__restrict__ x,
+                                                     long long npw, unsigned bpb,
+                                                     const double *__restrict__ w,
+                                                     const double *__restrict__ scale,
+                                                     double factor,
+                                                     typename Cplx<T>::type *__restrict__ y)
 {
-    const double f0 = factor * (scale ? scale[0] : 1.0);
-    const long long tot = npw * nb;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long n = i / npw;
-        const T f = (T)(f0 * (w ? w[n] : 1.0));
-        auto v = x[i];
-        v.x *= f;
-        v.y *= f;
-        y[i] = v;
-    }
+    const unsigned n = blockIdx.x / bpb, part = blockIdx.x - n * bpb;
+    const T f = (T)(factor * (scale ? scale[0] : 1.0) * (w ? w[n] : 1.0));
+    const long long base = (long long)n * npw;
+    const long long g0 = (long long)part * 1024 + threadIdx.x;
+    typename Cplx<T>::type v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (g0 + 256 * u < npw) v[u] = x[base + g0 + 256 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (g0 + 256 * u < npw) {
+            v[u].x *= f;
+            v[u].y *= f;
+            y[base + g0 + 256 * u] = v[u];
+        }
 }
 
 static unsigned grid_for(long long n, unsigned cap = 4096)
@@ -187,8 +218,11 @@ hipError_t launch_scale_bands(const void *x, int64_t npw, int64_t nb, const doub
 {
     if (nb <= 0) return hipSuccess;
     using C = typename Cplx<T>::type;
-    hipLaunchKernelGGL(k_scale_bands<T>, dim3(grid_for(npw * nb)), dim3(256), 0, st,
-                       reinterpret_cast<const C *>(x), (long long)npw, (long long)nb, w, scale,
+    if (npw <= 0) return hipSuccess;
+    const int64_t bpb = (npw + 1023) / 1024;
+    if (bpb * nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scale_bands<T>, dim3((unsigned)(bpb * nb)), dim3(256), 0, st,
+                       reinterpret_cast<const C *>(x), (long long)npw, (unsigned)bpb, w, scale,
                        factor, reinterpret_cast<C *>(y));
     return hipGetLastError();
 }

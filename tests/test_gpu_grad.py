@@ -226,6 +226,38 @@ def test_density_register_sums_128_f64_parted():
     assert relerr(rho3.cpu().numpy(), rho.cpu().numpy()) <= 1e-13
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("grid,ecut,nb", [((24, 24, 24), 0.4, 3), ((24, 24, 24), 3.0, 5),
+                                          ((24, 24, 24), 18.0, 4), ((48, 48, 48), 40.0, 3),
+                                          ((128, 128, 128), 512.0, 2)])
+def test_band_dot_and_scale_bands_vs_numpy(precision, grid, ecut, nb):
+    """The band energies and the band scaling on spheres of 1, 81, 925, 2969 and
+    137,065 plane waves (every remainder of the 1024-wide steps and several
+    blocks per band): Re <a_n|b_n> in FP64 against numpy on the same (rounded)
+    values to 1e-13; factor * scale * w_n * x_n bit-exact, since the factor is
+    rounded to the plan's precision once and each element takes one multiply."""
+    label(test="band_kernels", grid=grid, npw_ecut=ecut, precision=precision)
+    cell = synth.cubic_cell()
+    plan = vloc.Plan(grid, cell, ecut, precision=precision)
+    hkl = oracle.sphere_py(cell, ecut)
+    ct, cnp, rnp = (torch.complex128, np.complex128, np.float64) if precision == "f64" else \
+        (torch.complex64, np.complex64, np.float32)
+    rng = np.random.default_rng(11)
+    a = (rng.standard_normal((nb, hkl.shape[0])) + 1j * rng.standard_normal((nb, hkl.shape[0]))).astype(cnp)
+    b = (rng.standard_normal((nb, hkl.shape[0])) + 1j * rng.standard_normal((nb, hkl.shape[0]))).astype(cnp)
+    w = synth.band_weights(nb)
+    ta, tb = torch.from_numpy(a).to("cuda", ct), torch.from_numpy(b).to("cuda", ct)
+    e = plan.band_dot(ta, tb)
+    sc = torch.tensor([0.75], dtype=torch.float64, device="cuda")
+    y = plan.scale_bands(ta, w=torch.from_numpy(w).cuda(), scale=sc, factor=2.0)
+    torch.cuda.synchronize()
+    ref = np.real(np.sum(np.conj(a.astype(np.complex128)) * b.astype(np.complex128), axis=1))
+    assert np.max(np.abs(e.cpu().numpy() - ref) / np.abs(ref).max()) <= 1e-13
+    f = (2.0 * 0.75 * w).astype(rnp)
+    want = (a.real * f[:, None]) + 1j * (a.imag * f[:, None])
+    assert np.array_equal(y.cpu().numpy(), want.astype(cnp))
+
+
 def _energy(plan, c, V, w):
     with torch.no_grad():
         return ag.local_energy(plan, c, V, w).item()

@@ -290,19 +290,29 @@ def measure_grad(steps, warmup):
     import torch
 
     import synth
-    from paper_1601_07378_amd import autograd, vloc
+    from paper_1601_07378_amd import autograd, autotune, vloc
 
     w_ = synth.WORKLOADS["c5_128"]
     grid, cell, ecut, nb = w_["grid"], synth.cubic_cell(), synth.ecut_for_radius(w_["R"]), w_["nbands"]
     res = {}
+    splits = ("L1x", "L2x", "L1y", "L2y", "L1z", "L2z")
     for prec in ("f32", "f64"):
         ct, rt = (torch.complex128, torch.float64) if prec == "f64" else \
             (torch.complex64, torch.float32)
-        # the planner's schedule: the stored 128^3 schedules were tuned on the
-        # application alone, and their splits have compiled kernels for it only
-        # (the density passes of a step would run the runtime-sized kernels)
-        knobs, source = {}, "planner default"
+        # the stored schedule (tuned on the application) when it keeps the
+        # planner's line splits: the density kernels are compiled for those, and
+        # another split would send the density passes of a step to the
+        # runtime-sized kernels; else the planner's schedule
         plan = vloc.Plan(grid, cell, ecut, precision=prec)
+        knobs, source = schedule(grid, cell, ecut, [(0.0, 0.0, 0.0)], [nb], prec)
+        if knobs:
+            tuned_plan = vloc.Plan(grid, cell, ecut, precision=prec, **autotune.to_options(knobs))
+            if all(tuned_plan.layout()[k] == plan.layout()[k] for k in splits):
+                plan.close()
+                plan = tuned_plan
+            else:
+                tuned_plan.close()
+                knobs, source = {}, "planner default (the stored schedule changes the line splits)"
         c = torch.from_numpy(synth.coefficients(plan.gvectors(), nb)).to("cuda", ct)
         V = torch.from_numpy(synth.potential(grid, w_["ngauss"])).to("cuda", rt)
         w = torch.from_numpy(synth.band_weights(nb)).to("cuda", torch.float64)

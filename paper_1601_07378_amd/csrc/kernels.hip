@@ -2737,23 +2737,16 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
             }
         }
         const int nt = threads < 512 ? threads : 512;
-        // FP32 density with a plane that leaves one workgroup per CU (so 256
-        // registers per thread) and at most two x stage-B tasks per thread:
-        // the density sums stay in registers over the bands of a work item.
-        // The fused application + density takes the scatter y form there: with
-        // the direct form's prefetch registers as well it would spill.
+        // FP32 density with a plane that leaves one workgroup per CU: 1024
+        // threads (128 registers each), one x stage-B task per thread, and the
+        // density sums of a work item held in registers; the y passes in the
+        // scatter form (the direct form's prefetch registers would spill)
         constexpr bool DAK = std::is_same<T, float>::value &&
                              (MODE == MODE_DENSITY || MODE == MODE_APPLY_DENSITY) && X1 > 0 &&
                              Y1 > 0 && 8LL * X1 * X2 * Y1 * Y2 > 80 * 1024 && X1 * Y1 * Y2 <= 1024;
         if constexpr (DAK && !W)
-            if (2LL * lds > 160 * 1024 && X1 * Y1 * Y2 <= 2 * nt) {
-                if constexpr (MODE == MODE_DENSITY)
-                    if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
-                        return go(
-                            k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G, 2>,
-                            nt);
-                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 0, G, 2>, nt);
-            }
+            if (2LL * lds > 160 * 1024 && threads >= 512)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0, G, 1>, 1024);
         if constexpr (DYK && !W && std::is_same<T, float>::value)
             if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);

@@ -145,15 +145,15 @@ def test_apply_density_one_pass(precision, name, grid, cell, ecut, k, nb):
 
 @pytest.mark.parametrize("ysplit", [0, 8])
 def test_density_register_sums_128_f32(ysplit):
-    """FP32 density at 128^3 (|G| <= 32), where the whole plane leaves one
-    512-thread workgroup per CU and each thread keeps the density sums of a
-    work item (one z-plane, one band subset) in registers: 7 bands in launches
-    of 5 and 2 (subsets of 3 + 2 bands, then 1 + 1) against the oracle; the
+    """FP32 density at 128^3 (|G| <= 32), where the whole plane fills a CU's LDS
+    and the density kernels run 1024 threads, each keeping the density sums of
+    its x stage-B task over a work item (one z-plane, one band subset) in
+    registers: 7 bands in launches of 5 and 2 (subsets of 3 + 2 bands, then
+    1 + 1) against the oracle; the
     fused application + density equals the separate calls, and 256-thread
     workgroups (per-band sums into the partial plane, another y layout, so
     psi differs by FP32 rounding) agree to the FP32 level.  Both compiled y
-    splits: 16 x 8 (the density-only pass in the direct y form) and 8 x 16
-    (scatter form throughout)."""
+    splits, 16 x 8 and 8 x 16."""
     grid, cell, ecut = (128, 128, 128), synth.cubic_cell(), 512.0
     label(test="density_registers_128_f32", ysplit=ysplit)
     hkl = oracle.sphere_py(cell, ecut)

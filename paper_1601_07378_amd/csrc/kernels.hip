@@ -2747,6 +2747,14 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
         if constexpr (DAK && !W)
             if (2LL * lds > 160 * 1024 && threads >= 512)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 0, G, 1>, 1024);
+        // FP32 application on such planes: 1024 threads as well (128 registers
+        // each, no spill in the direct y form)
+        constexpr bool A1K = std::is_same<T, float>::value && MODE == MODE_APPLY && X1 > 0 &&
+                             Y1 > 0 && 8LL * X1 * X2 * Y1 * Y2 > 80 * 1024;
+        if constexpr (A1K && !W)
+            if (2LL * lds > 160 * 1024 && threads >= 512 && dyok &&
+                L.seg[0].nxo * g.L2y <= 1024)
+                return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1, G>, 1024);
         if constexpr (DYK && !W && std::is_same<T, float>::value)
             if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);

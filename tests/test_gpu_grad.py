@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import relerr
+from helpers import relerr, relerr_per_band
 
 pytestmark = pytest.mark.gpu
 
@@ -185,6 +185,11 @@ def test_density_register_sums_128_f32(ysplit):
     print("128^3 f32 density err: register sums", err, "per-band sums", err3)
     assert err <= 3e-6 and err3 <= 3e-6
     assert relerr(rho3.cpu().numpy(), rho.cpu().numpy()) <= 1e-6
+    # the application itself (1024-thread whole-plane kernel) against the oracle
+    err_out = relerr_per_band(ref_out.cpu().numpy().astype(np.complex128),
+                              oracle.apply(grid, cell, ecut, (0, 0, 0), c, V)).max()
+    print("128^3 f32 apply err", err_out)
+    assert err_out <= 2e-6
 
 
 def test_density_register_sums_128_f64_parted():

@@ -192,6 +192,36 @@ def test_density_register_sums_128_f32(ysplit):
     assert err_out <= 2e-6
 
 
+def test_f32_128_k_shifted_1024_thread_kernels_vs_oracle():
+    """A k-shifted 128^3 FP32 plan (64 occupied x-planes, y split 8 x 16): the
+    1024-thread application kernel (direct y form, 64 x 16 y tasks) and the
+    1024-thread density kernels with register sums, against the oracle."""
+    grid, cell, ecut, k = (128, 128, 128), synth.cubic_cell(), 512.0, (0.25, 0.25, 0.25)
+    label(test="f32_128_k_1024", k=k)
+    hkl = oracle.sphere_py(cell, ecut, k)
+    nb = 3
+    c = synth.coefficients(hkl, nb, k).astype(np.complex64).astype(np.complex128)
+    V = synth.potential(grid, 8).astype(np.float32).astype(np.float64)
+    w = synth.band_weights(nb)
+    plan = vloc.Plan(grid, cell, ecut, k, precision="f32")
+    lay = plan.layout()
+    assert lay["plane_xmode"] == 3 and lay["nxo"] == 64 and (lay["L1y"], lay["L2y"]) == (8, 16)
+    tc = torch.from_numpy(c).to("cuda", torch.complex64)
+    tV = torch.from_numpy(V).to("cuda", torch.float32)
+    tw = torch.from_numpy(w).cuda()
+    out = plan.apply(tc, tV)
+    out2, rho = plan.apply_density(tc, tV, tw)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    err = relerr_per_band(out.cpu().numpy().astype(np.complex128),
+                          oracle.apply(grid, cell, ecut, k, c, V)).max()
+    psi = oracle.g2r(grid, cell, ecut, k, c).reshape(nb, -1)
+    rho_or = (w[:, None] * np.abs(psi) ** 2).sum(0) / np.prod(grid)
+    err_rho = relerr(rho.cpu().numpy().ravel(), rho_or)
+    print("128^3 f32 k-shifted: apply err", err, "density err", err_rho)
+    assert err <= 2e-6 and err_rho <= 3e-6
+
+
 def test_density_register_sums_128_f64_parted():
     """FP64 density at 128^3 (|G| <= 32) on the parted plane (two parts of 64
     rows): the density kernels run 512 threads and keep the sums of a work

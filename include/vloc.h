@@ -96,9 +96,10 @@ typedef struct {
                                  registers: 512 for the FP64 parted plane with x
                                  split 8 x 16, y split 16 x 8 and two parts (when
                                  plane_threads >= 512); where the FP32 whole
-                                 plane fills a CU's LDS, its application and
-                                 density kernels run 1024 (when plane_threads
-                                 >= 512)                                         */
+                                 plane leaves one workgroup per CU (more than
+                                 80 KiB of LDS), the application runs 1024, and
+                                 so do the density kernels of the compiled 128^2
+                                 planes (when plane_threads >= 512)              */
     int32_t plane_xwaves;     /* wavefronts of the plane workgroup that run the x
                                  pass (each with its own row buffer); 0 = auto     */
     int32_t plane_xmode;      /* layout of the plane kernel: 0 = automatic (3 where

@@ -2755,6 +2755,12 @@ static hipError_t launch_plane_full(const Geometry &g, const DevTables &t, const
             if (2LL * lds > 160 * 1024 && threads >= 512 && dyok &&
                 L.seg[0].nxo * g.L2y <= 1024)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 1024, W, 1, G>, 1024);
+        // the same for the runtime-sized FP32 application (codelets of at most
+        // 16 points, scatter y form)
+        if constexpr (std::is_same<T, float>::value && MODE == MODE_APPLY && X1 == 0 && !W)
+            if (2LL * lds > 160 * 1024 && threads >= 512 && plane_codelet_max(g) <= 16)
+                return go(k_plane_full<T, MODE, 0, 0, 0, 0, 0, 0, 0, 1024, W, 0, G ? G : 16>,
+                          1024);
         if constexpr (DYK && !W && std::is_same<T, float>::value)
             if (dyok && L.seg[0].nxo * g.L2y <= 2 * nt)
                 return go(k_plane_full<T, MODE, X1, X2, Y1, Y2, ZX, FX, ZY, 512, W, 2, G>, nt);

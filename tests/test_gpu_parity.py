@@ -347,6 +347,32 @@ def test_tuner_split_kernels_vs_oracle(precision):
 
 # --------------------------- runtime-sized kernels, by codelet class
 
+@pytest.mark.parametrize("grid,radius,split,cls", [
+    ((100, 100, 100), 25.0, (0, 0, 0), 10),   # 10 x 10 lines
+    ((108, 108, 108), 27.0, (0, 0, 0), 12),   # 9 x 12
+    ((120, 120, 120), 30.0, (0, 0, 0), 12),   # 10 x 12
+    ((128, 128, 128), 32.0, (16, 0, 0), 16),  # x 16 x 8, not compiled for the whole plane
+])
+def test_runtime_sized_f32_one_workgroup_per_cu_vs_oracle(grid, radius, split, cls):
+    """FP32 planes of more than 80 KB (one workgroup per CU) with no compiled
+    specialisation: the application runs the runtime-sized kernel on 1024
+    threads; against the oracle on FP32-rounded inputs."""
+    cell, k = synth.cubic_cell(), (0.0, 0.0, 0.0)
+    ecut = synth.ecut_for_radius(radius)
+    label(test="runtime_sized_1024", grid=grid, split=split)
+    hkl, c, V = case(grid, cell, ecut, k, 2)
+    p = vloc.Plan(grid, cell, ecut, k, precision="f32", split=split)
+    lay = p.layout()
+    assert lay["plane_xmode"] == 3 and lay["plane_lds_bytes"] > 80 * 1024
+    assert max(lay["L1x"], lay["L2x"], lay["L1y"], lay["L2y"]) <= cls
+    got = run(p, c, V)
+    ref = oracle.apply(grid, cell, ecut, k, c.astype(np.complex64).astype(np.complex128),
+                       V.astype(np.float32).astype(np.float64))
+    err = relerr_per_band(got, ref)
+    print(grid, split, "f32 runtime-sized 1024 err", err.max())
+    assert err.max() <= TOL32
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("grid,ecut,split,cls", [
     ((20, 24, 18), 12.0, (2, 0, 0), 10),     # x = 2 x 10, y = 4 x 6: the <= 10 class

@@ -83,7 +83,9 @@ typedef struct {
     int32_t sticks_per_group; /* 0 = automatic; else 1..64                         */
     int32_t band_chunk;       /* most bands (band pairs in the real mode) per launch;
                                  a call is cut into equal chunks of at most this
-                                 many; 0 = automatic (stick buffer <= 256 MiB)     */
+                                 many; 0 = automatic (stick buffer <= 256 MiB, and
+                                 <= 176 MiB in the density passes, whose FP64
+                                 partial planes share the last-level cache)       */
     int32_t plane_rows;       /* rows per x-pass batch of one wavefront in the plane
                                  kernel (plane_xmode 1), rows per part N2 / P
                                  (plane_xmode 6); 0 = automatic                    */

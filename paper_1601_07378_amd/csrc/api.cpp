@@ -577,7 +577,7 @@ vloc_status run_launches(Engine &E, int mode, const Launch *ls, size_t nl, const
 
 // One plan: its bands in chunks of the plan's band_chunk.
 vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, const void *V,
-                     void *out, const double *wts = nullptr)
+                     void *out, const double *wts = nullptr, int64_t max_chunk = 0)
 {
     Engine &E = p->eng;
     vloc_status s = upload(E);
@@ -589,7 +589,8 @@ vloc_status dispatch(vloc_plan p, int mode, const void *in, int64_t nbands, cons
                          : nullptr};
     // equal chunks of at most band_chunk launch bands (no short last chunk)
     const int64_t units = p->hp.gamma ? (nbands + 1) / 2 : nbands;
-    const int64_t nch = (units + p->hp.band_chunk - 1) / p->hp.band_chunk;
+    const int64_t bc = max_chunk > 0 ? max_chunk : p->hp.band_chunk;
+    const int64_t nch = (units + bc - 1) / bc;
     const int64_t chunk = nch > 0 ? (units + nch - 1) / nch : 1;
     size_t need = make_launches(E, ins, outs, &nbands, chunk, ls);
     if ((s = ensure_scratch(E, need)) != VLOC_OK) return s;
@@ -894,7 +895,8 @@ vloc_status density_pass(vloc_plan plan, int mode, const void *c, int64_t nbands
     HostPlan &h = plan->hp;
     Geometry &g = E.geo;
     const int64_t N = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
-    const int64_t chunk = nbands < h.band_chunk ? nbands : h.band_chunk;
+    const int64_t dchunk = h.density_chunk > 0 ? h.density_chunk : h.band_chunk;
+    const int64_t chunk = nbands < dchunk ? nbands : dchunk;
     // band subsets per launch: items N3 * nsub fill the resident workgroups in
     // whole rounds where possible (fewest idle slots, then fewest subsets)
     {
@@ -931,7 +933,7 @@ vloc_status density_pass(vloc_plan plan, int mode, const void *c, int64_t nbands
     }
     hipError_t e = launch_fill_f64(E.d_partial, (int64_t)g.nsub * N, 0.0, E.stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
-    s = dispatch(plan, mode, c, nbands, V, out, w);
+    s = dispatch(plan, mode, c, nbands, V, out, w, dchunk);
     if (s != VLOC_OK) return s;
     e = launch_density_reduce(g, E.d_partial, g.nsub, scale, rho, E.stream);
     return e == hipSuccess ? VLOC_OK : hip_fail(e, "density reduce launch");

@@ -708,6 +708,13 @@ vloc_status build_host_plan(HostPlan &p, const int32_t grid[3], const double cel
     // stick-kernel blocks of one launch (chunk * ngroups) stay below 2^31
     chunk = std::min<int64_t>(chunk, INT32_MAX / std::max<int32_t>(1, p.ngroups));
     p.band_chunk = (int32_t)std::min<int64_t>(chunk, 1 << 20);
+    // the density passes also keep the FP64 partial planes live, which share
+    // the device's 256 MB last-level cache with the stick buffer: there the
+    // automatic chunk keeps the stick buffer within 176 MiB (measured at 128^3:
+    // 54 instead of 81 FP32 bands per launch, 27 instead of 40 FP64)
+    int64_t dchunk = std::max<int64_t>(1, (176LL << 20) / per_band);
+    p.density_chunk = p.opt.band_chunk ? p.band_chunk
+                                       : (int32_t)std::min<int64_t>(dchunk, p.band_chunk);
     return VLOC_OK;
 }
 

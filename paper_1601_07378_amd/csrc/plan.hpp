@@ -52,6 +52,7 @@ struct HostPlan {
 
     Split sx, sy, sz;
     int32_t band_chunk = 0;   // bands per internal chunk
+    int32_t density_chunk = 0; // bands per chunk of the density passes
     int32_t plane_rows = 0;   // x-pass rows per batch in the plane kernel
     int32_t plane_threads = 0;
     int32_t plane_lds = 0;    // bytes of LDS per plane workgroup
